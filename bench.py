@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Throughput of the adaptive Brillouin-zone quadrature on one MI355X.
+
+One step = one call of the library over the whole realistic workload: t=1,
+t'=-0.25, mu=-0.95 (near van Hove), T=0.01, 20 flow scales log-spaced from 10
+to 0.01, 24x24 transfer momenta, 9 form factors, both channels, rtol 1e-6:
+23,040 containers, 1,036,800 integrals.  Inputs are synthetic (seeded, see
+workloads/), outputs stay in device memory.
+
+Prints one JSON line with the metric, a roofline entry for the dominant
+kernel (region evaluation, timed with HIP events on its launch stream inside
+the library) and the oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "integrals/s at rtol 1e-6, plain vs batched+learned-seeded, 1 MI355X"
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (vector and matrix)
+
+# Algorithmic work of one region-evaluation work item (a parent and its four
+# children, rule pair N = 4 / 2N = 8, shared 17 x 17 node grid):
+#   integrand: 289 nodes x 118 FP64 flops (dispersion 12, switch 8, map 4,
+#              three Horner chains of degree 15 = 90, combine 4);
+#   projection: 4 children x 2 M^2 (n_2N + n_N) = 4 x 2 M^2 (81 + 25).
+K_FLOPS_PER_NODE = 118
+NODES_PER_ITEM = 289
+
+
+def item_flops(M: int) -> int:
+    return NODES_PER_ITEM * K_FLOPS_PER_NODE + 4 * 2 * M * M * (81 + 25)
+
+
+def cpu_baseline(cfg, budget_s: float, threads: int, seed: int = 11):
+    """The oracle as it stands on a seeded sample of the same workload:
+    every flow scale, `nq` random transfer momenta of the grid, both channels."""
+    import oracle as O
+    import workloads as W
+    rng = np.random.default_rng(seed)
+    nq = 4
+    qi = rng.choice(len(cfg["q"]), size=nq, replace=False)
+    conts = []
+    for p in cfg["params"]:
+        for i in qi:
+            for ch in (O.PP, O.PH):
+                conts.append(O.Container(cfg["ff"], cfg["L"], t=p[0], tp=p[1], mu=p[2], T=p[3],
+                                         Omega=p[4], lx=cfg["q"][i][0], ly=cfg["q"][i][1],
+                                         channel=ch))
+    M = cfg["ff"].shape[0]
+    t0 = time.perf_counter()
+    _, _, sts, nc = O.integrate_batch(conts, rtol=cfg["rtol"], err_mode=O.ERR_GLOBAL, batch=1,
+                                      nthreads=threads)
+    dt = time.perf_counter() - t0
+    n_int = len(conts) * M * (M + 1) // 2
+    return {"value": n_int / dt, "unit": "integrals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(conts)} containers of the same workload (all 20 scales x {nq} "
+                      f"seeded q x 2 channels), serial Alg. 2 per container, OpenMP over "
+                      f"containers, {dt:.1f} s wall, budget {budget_s:.0f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--variants", action="store_true", help="also time one call per flow scale")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the containers would shard across GPUs with no exchange during integration",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paid_1610_09991_amd as P
+    import workloads as W
+
+    cfg = W.config(args.workload)
+    params, q, ff, L = cfg["params"], cfg["q"], cfg["ff"], cfg["L"]
+    M = ff.shape[0]
+    MU = M * (M + 1) // 2
+    nch = 2
+    n_ctr = len(params) * len(q) * nch
+    n_int = n_ctr * MU
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = P.Context(stream=stream.cuda_stream, profile=1)
+    out = torch.empty((len(params), len(q), nch, M, M), dtype=torch.float64, device=dev)
+    run = lambda o: ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=o)
+
+    for i in range(args.warmup):
+        _, _, st, rc = run(out)
+        print(f"# warmup {i}: {st['seconds']:.3f} s, regions {st['regions']}, rc {rc}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        _, _, st, rc = run(out)
+        stats.append(st)
+        print(f"# step {i}: {st['seconds']:.3f} s, regions {st['regions']}, rc {rc}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / args.steps
+    value = n_int * args.steps / dt
+
+    items = sum(s["eval_items"] for s in stats)
+    ev_s = sum(s["eval_seconds"] for s in stats)
+    launches = sum(s["eval_launches"] for s in stats)
+    flops_launch = item_flops(M) * items / max(launches, 1)
+    avg_launch = ev_s / max(launches, 1)
+    achieved = flops_launch / avg_launch / 1e12 if avg_launch > 0 else 0.0
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "kernel": "k_children (region evaluation)", "launches": launches,
+            "avg_launch_ms": 1e3 * avg_launch, "flops_per_item": item_flops(M),
+            "items": items, "eval_share_of_step": ev_s / dt}
+
+    line = {"metric": METRIC, "value": value, "unit": "integrals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"{cfg['name']}: {cfg['desc']}", "containers": n_ctr,
+                       "integrals_per_step": n_int, "variant": "batched (all containers in one "
+                       "call)", "err_mode": "global", "rule": "Clenshaw-Curtis N=4/2N=8",
+                       "regions_per_step": stats[-1]["regions"],
+                       "splits_per_step": stats[-1]["splits"]},
+            "roofline": roof}
+
+    if args.variants:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for p in params:  # plain: one call per flow scale
+            ctx.integrate(p[None, :], q, ff, L, P.PP | P.PH, rtol=cfg["rtol"])
+        torch.cuda.synchronize()
+        line["variants"] = {"plain_per_scale": n_int / (time.perf_counter() - t1)}
+
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget, threads)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

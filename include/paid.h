@@ -1,0 +1,182 @@
+/*
+ * paid.h -- C ABI of libpaid, the MI355X (gfx950) implementation of the
+ * adaptive Brillouin-zone quadrature of the scale-derivative bubbles of the
+ * truncated-unity fRG (arXiv:1610.09991).
+ *
+ * What is computed (Sec. 2, Eqs. chi_pp and chi_ph, with the dot of the
+ * flow equations): for every container = (parameter row, transfer momentum
+ * l = q, channel j in {pp, ph}) and every pair of form factors (m, n)
+ *
+ *   chidot^j_mn(l) = int_{[-pi,pi)^2} d^2p/(2pi)^2  g_j(p) f_m(p) f_n(p),
+ *   g_j(p) = T sum_{w_n} d/dOmega [theta(w_n)^2] G-product_j,
+ *   theta(w) = w^2/(w^2+Omega^2),  w_n = (2n+1) pi T,
+ *   ph: 1/((i w - a)(i w - b)),  pp: 1/((i w - a)(-i w - b)),
+ *   a = eps(l/2 + p),  b = eps(l/2 - p),
+ *   eps(k) = -2t(cos kx + cos ky) - 4t' cos kx cos ky - mu.
+ *
+ * How (Secs. 3-4, Alg. 2): nested Clenshaw-Curtis pair Q_N / Q_2N on every
+ * rectangle (N intervals per axis, the coarse nodes a subset of the fine
+ * ones), error |Q_N - Q_2N|, worst-error-first subdivision of rectangles
+ * into 2x2 children with bulk extraction (the MaxTask analogue), global
+ * error criterion over all form-factor pairs of a container, result the sum
+ * of Q_2N over the leaves.  All containers of a call run together on the GPU.
+ *
+ * Conventions for every entry point:
+ *   - return value: PAID_OK (0), a positive warning, or a negative error;
+ *     the message of the last failure is paid_last_error(ctx);
+ *   - input arrays are read-only and owned by the caller; output arrays are
+ *     owned by the caller and fully written on PAID_OK and PAID_ENOCONV;
+ *   - pointers may be host or device (HIP) memory unless stated otherwise;
+ *     the library detects which;
+ *   - calls on one context are serialised on the context's stream and are
+ *     synchronous: on return the outputs are complete;
+ *   - one context per host thread; contexts are independent.
+ */
+#ifndef PAID_H
+#define PAID_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  PAID_OK = 0,
+  PAID_ENOCONV = 1,    /* warning: some container hit max_regions; outputs hold
+                          the best value and its error estimate */
+  PAID_EINVAL = -1,    /* invalid argument */
+  PAID_ENOMEM = -2,    /* device memory exhausted */
+  PAID_EDEVICE = -3,   /* HIP runtime error (message has the HIP error string) */
+  PAID_EINTERNAL = -4
+};
+
+/* integrand kinds */
+enum {
+  PAID_BUBBLE_DOT = 0, /* d/dOmega of the regulated bubble: the flow integrand */
+  PAID_BUBBLE = 1,     /* the regulated bubble itself (theta^2 G G) */
+  PAID_UNIT = 2,       /* g = 1 (integral of f_m f_n), for checks */
+  PAID_GAUSS = 3       /* g = exp(-|p - p0|^2/(2 sigma^2)), for checks */
+};
+
+/* channel bits of paid_integrate's `channels` */
+enum { PAID_PP = 1, PAID_PH = 2 };
+
+/* termination test (Sec. 3 and Alg. 2) */
+enum {
+  PAID_ERR_GLOBAL = 0,       /* sum over pairs and leaves of |Q_N - Q_2N| <=
+                                max(atol, rtol * sum over pairs |value|)  (the
+                                paper's global criterion) */
+  PAID_ERR_PER_INTEGRAL = 1  /* every pair: sum over leaves of its error <=
+                                max(atol, rtol * max(|value_pq|, nu max |value|)) */
+};
+
+/* arithmetic of the form-factor projection */
+enum {
+  PAID_FP64 = 0,   /* everything in FP64 */
+  PAID_FP32 = 1,   /* projection in FP32 on the matrix cores, FP64 sums */
+  PAID_BF16X3 = 2  /* projection with three-term bf16 splits, FP32 accumulate */
+};
+
+/* how the projection F^T diag(w g) F is formed */
+enum {
+  PAID_GRAM_MFMA = 0,      /* dense weighted Gram contraction on the matrix cores */
+  PAID_GRAM_SEPARABLE = 1  /* the same sums factored along the two axes (FP64 only) */
+};
+
+typedef struct {
+  int device;           /* HIP device ordinal */
+  int N;                /* coarse rule: N intervals per axis (fine: 2N); 4 */
+  int batch;            /* minimum leaves split per container per round
+                           (the MaxTask analogue), >= 1 */
+  int batch_max;        /* maximum leaves split per container per round */
+  int err_mode;         /* PAID_ERR_* */
+  int precision;        /* PAID_FP64 / PAID_FP32 / PAID_BF16X3 */
+  int gram;             /* PAID_GRAM_* */
+  int kind;             /* PAID_BUBBLE_DOT (default), ... */
+  double nu;            /* floor factor of PAID_ERR_PER_INTEGRAL */
+  long max_regions;     /* leaf budget per container */
+  int max_active;       /* containers resident at once (0: from pool size) */
+  double pool_gib;      /* region pool size in GiB (0: a share of free memory) */
+  double gauss[3];      /* PAID_GAUSS centre (x, y) and width */
+  void *stream;         /* hipStream_t to run on, or NULL for a private stream */
+  int profile;          /* 1: time the region-evaluation launches with HIP
+                           events on the context stream (paid_stats.eval_*) */
+} paid_config;
+
+/* one parameter row: dispersion, temperature and flow scale */
+typedef struct {
+  double t, tp, mu, T, Omega;
+} paid_params;
+
+typedef struct {
+  long containers;      /* containers integrated */
+  long not_converged;   /* containers that hit max_regions */
+  long regions;         /* leaves at exit, summed over containers */
+  long splits;          /* rectangles subdivided, summed */
+  long kernel_evals;    /* evaluations of the scalar integrand g */
+  long rounds;          /* bulk-extraction rounds, summed over containers */
+  long launch_rounds;   /* device rounds of the whole call */
+  int max_depth;        /* deepest subdivision level */
+  int max_active;       /* containers resident at once */
+  double seconds;       /* wall time of the call */
+  double eval_seconds;  /* profile: summed duration of the region-evaluation launches */
+  long eval_launches;   /* profile: number of those launches */
+  long eval_items;      /* parents evaluated (each gives 4 children) */
+} paid_stats;
+
+/* Fill *cfg with defaults (device 0, N = 4, batch 8, batch_max 1024, global
+ * error, FP64, MFMA Gram, nu = 1e-3, max_regions = 2^18, automatic pool). */
+int paid_config_default(paid_config *cfg);
+
+/* Create a context on cfg->device.  *out receives the context (NULL on
+ * failure).  The context owns its device workspace, tables and stream. */
+int paid_create(struct paid_ctx **out, const paid_config *cfg);
+
+/* Integrate every container of the batch (Alg. 2 over all containers).
+ *   params   [n_params] parameter rows (t > 0 not required; T > 0, Omega >= 0)
+ *   q        [n_q][2]   transfer momenta l in radians (not reduced mod 2pi)
+ *   ff       [n_ff][(2 ff_L + 1)^2] form factors as coefficients over the
+ *            box basis u_a(p_x) u_b(p_y), u_0 = 1, u_{2k-1} = sqrt2 cos kx,
+ *            u_{2k} = sqrt2 sin kx; rows must be orthonormal (to 1e-12);
+ *            0 <= ff_L <= 2, 1 <= n_ff <= (2 ff_L + 1)^2
+ *   channels PAID_PP | PAID_PH (at least one)
+ *   rtol, atol  tolerance of the termination test (rtol > 0 or atol > 0)
+ *   out      [n_params][n_q][n_ch][n_ff][n_ff] FP64, both halves written,
+ *            channel order pp before ph
+ *   err_out  NULL or the same shape: per pair, sum over leaves of
+ *            |Q_N - Q_2N|
+ *   stats    NULL or filled on return
+ * Returns PAID_OK, PAID_ENOCONV, or an error (outputs then undefined). */
+int paid_integrate(struct paid_ctx *ctx, const paid_params *params, int n_params,
+                   const double *q, int n_q, const double *ff, int n_ff, int ff_L,
+                   unsigned channels, double rtol, double atol, double *out,
+                   double *err_out, paid_stats *stats);
+
+/* Frequency-summed kernel g = K_j(a, b) of one parameter row at n energy
+ * pairs (the closed-form frequency sum of Sec. 2 as the library evaluates
+ * it).  channel: PAID_PP or PAID_PH.  a, b, out: [n]. */
+int paid_kernel_eval(struct paid_ctx *ctx, const paid_params *p, unsigned channel,
+                     const double *a, const double *b, int n, double *out);
+
+/* Evaluate the four children of n parent rectangles of one container with
+ * the same device code paid_integrate uses (Sec. 3 rule pair on each child).
+ * A rectangle is coded as (depth, ix, iy): x in [-pi + 2pi ix/2^depth,
+ * -pi + 2pi (ix+1)/2^depth), likewise y.  codes: [n][3] int.
+ * q2n: [n][4][n_ff (n_ff+1)/2] upper-triangle pairs, row-major;
+ * err: [n][4] key of each child (sum over pairs of |Q_N - Q_2N|).  Children
+ * are ordered (x-lo,y-lo), (x-hi,y-lo), (x-lo,y-hi), (x-hi,y-hi). */
+int paid_children_eval(struct paid_ctx *ctx, const paid_params *p, const double *l,
+                       unsigned channel, const double *ff, int n_ff, int ff_L,
+                       const int *codes, int n, double *q2n, double *err);
+
+/* Release the context and everything it owns.  NULL is accepted. */
+void paid_destroy(struct paid_ctx *ctx);
+
+/* Message of the last failure on ctx (or of the last paid_create failure
+ * when ctx is NULL).  Valid until the next call on the same context. */
+const char *paid_last_error(const struct paid_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,699 @@
+// api.hip -- the C ABI of libpaid (declared in include/paid.h): argument
+// checks, device workspace, the round loop of the adaptive scheme (Alg. 2)
+// over all containers, and the diagnostic entry points.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "paid.h"
+
+using namespace paid;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n && p) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    size_t want = bytes ? bytes : 1;
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) n = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+}  // namespace
+
+struct paid_ctx {
+  paid_config cfg;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // workspace
+  DevBuf entries, tab, zeta, svals, ctr, qv, ffc;
+  DevBuf code, key, Q, E;
+  DevBuf slot_i, slot_d, sel, dv, de, dep, itau, errp, stl, counters, outs, errs;
+  int *host_counters = nullptr;  // pinned
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profile: around the evaluation launch
+};
+
+namespace {
+
+int fail(paid_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(paid_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf; else g_create_error = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      (void)hipGetLastError();                                                                \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? PAID_ENOMEM : PAID_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                          \
+    }                                                                                         \
+  } while (0)
+
+bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Clenshaw-Curtis rule with n intervals on [-1,1], ascending nodes; weights
+// from the moment conditions sum_k w_k T_j(x_k) = int_{-1}^{1} T_j, j = 0..n,
+// solved by Gaussian elimination (exact rule of interpolatory type).
+void cc_rule_ascending(int n, double *x, double *w) {
+  const double pi = 3.14159265358979323846;
+  std::vector<double> A((n + 1) * (n + 2));
+  for (int k = 0; k <= n; ++k) x[k] = sin(pi * (double)(2 * k - n) / (2.0 * n));
+  for (int j = 0; j <= n; ++j) {
+    for (int k = 0; k <= n; ++k) A[j * (n + 2) + k] = cos(j * acos(fmax(-1.0, fmin(1.0, x[k]))));
+    A[j * (n + 2) + n + 1] = (j % 2) ? 0.0 : 2.0 / (1.0 - (double)j * j);
+  }
+  for (int c = 0; c <= n; ++c) {  // partial pivoting
+    int piv = c;
+    for (int r = c + 1; r <= n; ++r)
+      if (fabs(A[r * (n + 2) + c]) > fabs(A[piv * (n + 2) + c])) piv = r;
+    for (int k = 0; k < n + 2; ++k) std::swap(A[c * (n + 2) + k], A[piv * (n + 2) + k]);
+    for (int r = 0; r <= n; ++r) {
+      if (r == c) continue;
+      double f = A[r * (n + 2) + c] / A[c * (n + 2) + c];
+      for (int k = c; k < n + 2; ++k) A[r * (n + 2) + k] -= f * A[c * (n + 2) + k];
+    }
+  }
+  for (int k = 0; k <= n; ++k) w[k] = A[k * (n + 2) + n + 1] / A[k * (n + 2) + k];
+  for (int k = 0; k <= n / 2; ++k) {  // symmetrise
+    double s = 0.5 * (w[k] + w[n - k]);
+    w[k] = w[n - k] = s;
+  }
+}
+
+int g_rule_ready[64] = {0};
+
+int ensure_rule(paid_ctx *c) {
+  int dev = c->cfg.device;
+  if (dev >= 0 && dev < 64 && g_rule_ready[dev]) return PAID_OK;
+  RuleConst rc;
+  double x1[kNCo];
+  cc_rule_ascending(kNF - 1, rc.xi, rc.w2);
+  cc_rule_ascending(kNCo - 1, x1, rc.w1);
+  HIPCHK(c, set_rule_constants(rc));
+  if (dev >= 0 && dev < 64) g_rule_ready[dev] = 1;
+  return PAID_OK;
+}
+
+constexpr double kPiH = 3.14159265358979323846;
+
+// host bookkeeping of one parameter row's table (sizes only; the table
+// itself is computed on the device)
+Entry make_entry(const paid_params &p, int kind, int &off) {
+  Entry e;
+  memset(&e, 0, sizeof e);
+  e.t = p.t;
+  e.tp = p.tp;
+  e.mu = p.mu;
+  e.T = p.T;
+  e.Om = p.Omega;
+  e.kind = kind;
+  e.emax = 4.0 * fabs(p.t) + 4.0 * fabs(p.tp) + fabs(p.mu);
+  if (kind <= 1) {
+    e.w = kPiH * p.T;
+    e.inv_w = 1.0 / e.w;
+    double top = e.emax * 1.01 + 1e-3 * e.w;
+    e.J = 1 + (int)ceil((asinh(top / e.w) - kTabS1) / kTabDs);
+    if (e.J < 1) e.J = 1;
+    double xJ = e.w * sinh(kTabS1 + (e.J - 1) * kTabDs);
+    double big = fmax(fmax(p.Omega, 1.6 * xJ), kPiH * p.T);
+    int nm = (int)ceil((4.0 * big / (kPiH * p.T) - 1.0) / 2.0);
+    e.nmats = nm < 8 ? 8 : nm;
+  } else {
+    e.w = 1.0;
+    e.inv_w = 1.0;
+    e.J = 1;
+    e.nmats = 0;
+  }
+  e.tab_off = off;
+  off += e.J * kTabStride;
+  return e;
+}
+
+int build_tables(paid_ctx *c, const paid_params *params, int n, int kind) {
+  std::vector<Entry> es(n);
+  int off = 0, maxJ = 1;
+  for (int i = 0; i < n; ++i) {
+    es[i] = make_entry(params[i], kind, off);
+    if (es[i].J > maxJ) maxJ = es[i].J;
+  }
+  HIPCHK(c, c->entries.ensure(sizeof(Entry) * n));
+  HIPCHK(c, c->tab.ensure(sizeof(double) * (size_t)off));
+  HIPCHK(c, c->zeta.ensure(sizeof(double) * (size_t)n * (kTabKTail + 1)));
+  HIPCHK(c, c->svals.ensure(sizeof(double2) * (size_t)n * maxJ * kTabPts));
+  HIPCHK(c, hipMemcpyAsync(c->entries.p, es.data(), sizeof(Entry) * n, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemsetAsync(c->tab.p, 0, sizeof(double) * (size_t)off, c->stream));
+  TabArgs a;
+  a.entries = c->entries.as<Entry>();
+  a.n_entries = n;
+  a.max_J = maxJ;
+  a.tab = c->tab.as<double>();
+  a.zeta = c->zeta.as<double>();
+  a.svals = c->svals.as<double2>();
+  HIPCHK(c, launch_tables(a, c->stream));
+  return PAID_OK;
+}
+
+int check_params(paid_ctx *c, const paid_params *p, int n, int kind) {
+  for (int i = 0; i < n; ++i) {
+    const paid_params &r = p[i];
+    if (!isfinite(r.t) || !isfinite(r.tp) || !isfinite(r.mu) || !isfinite(r.T) ||
+        !isfinite(r.Omega))
+      return fail(c, PAID_EINVAL, "params[%d] not finite", i);
+    if (kind <= 1 && !(r.T > 0.0)) return fail(c, PAID_EINVAL, "params[%d].T must be > 0", i);
+    if (kind <= 1 && !(r.Omega >= 0.0)) return fail(c, PAID_EINVAL, "params[%d].Omega must be >= 0", i);
+    if (kind <= 1 && r.T < 1e-6) return fail(c, PAID_EINVAL, "params[%d].T below 1e-6 is not supported", i);
+  }
+  return PAID_OK;
+}
+
+int check_ff(paid_ctx *c, const double *ff, int n_ff, int L, int &identity) {
+  if (L < 0 || L > kMaxL) return fail(c, PAID_EINVAL, "ff_L must be 0..%d", kMaxL);
+  int nb = (2 * L + 1) * (2 * L + 1);
+  if (n_ff < 1 || n_ff > nb) return fail(c, PAID_EINVAL, "n_ff must be 1..%d", nb);
+  identity = (n_ff == nb);
+  for (int i = 0; i < n_ff; ++i)
+    for (int j = 0; j < n_ff; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < nb; ++k) s += ff[i * nb + k] * ff[j * nb + k];
+      if (fabs(s - (i == j ? 1.0 : 0.0)) > 1e-12)
+        return fail(c, PAID_EINVAL, "form factors not orthonormal (row %d, %d)", i, j);
+    }
+  for (int i = 0; i < n_ff && identity; ++i)
+    for (int k = 0; k < nb; ++k)
+      if (ff[i * nb + k] != (i == k ? 1.0 : 0.0)) identity = 0;
+  return PAID_OK;
+}
+
+// host copy of an input array that may live on the device
+template <class T>
+int to_host(paid_ctx *c, const T *p, size_t n, std::vector<T> &out) {
+  out.resize(n);
+  if (n == 0) return PAID_OK;
+  if (is_device_ptr(p)) {
+    HIPCHK(c, hipMemcpy(out.data(), p, sizeof(T) * n, hipMemcpyDeviceToHost));
+  } else {
+    memcpy(out.data(), p, sizeof(T) * n);
+  }
+  return PAID_OK;
+}
+
+struct SlotLayout {  // carving of the small per-slot arrays
+  int *cid, *state, *nleaf, *selcnt, *woff, *flags, *depth;
+};
+
+}  // namespace
+
+extern "C" {
+
+int paid_config_default(paid_config *cfg) {
+  if (!cfg) return PAID_EINVAL;
+  memset(cfg, 0, sizeof *cfg);
+  cfg->device = 0;
+  cfg->N = 4;
+  cfg->batch = 8;
+  cfg->batch_max = 1024;
+  cfg->err_mode = PAID_ERR_GLOBAL;
+  cfg->precision = PAID_FP64;
+  cfg->gram = PAID_GRAM_MFMA;
+  cfg->kind = PAID_BUBBLE_DOT;
+  cfg->nu = 1e-3;
+  cfg->max_regions = 1L << 18;
+  cfg->max_active = 0;
+  cfg->pool_gib = 0.0;
+  cfg->gauss[2] = 1.0;
+  cfg->stream = nullptr;
+  return PAID_OK;
+}
+
+int paid_create(paid_ctx **out, const paid_config *cfg_in) {
+  if (!out) return fail(nullptr, PAID_EINVAL, "out is NULL");
+  *out = nullptr;
+  paid_config cfg;
+  if (cfg_in) cfg = *cfg_in; else paid_config_default(&cfg);
+  if (cfg.N != 4) return fail(nullptr, PAID_EINVAL, "only N = 4 is implemented");
+  if (cfg.batch < 1 || cfg.batch_max < cfg.batch)
+    return fail(nullptr, PAID_EINVAL, "need 1 <= batch <= batch_max");
+  if (cfg.err_mode != PAID_ERR_GLOBAL && cfg.err_mode != PAID_ERR_PER_INTEGRAL)
+    return fail(nullptr, PAID_EINVAL, "bad err_mode");
+  if (cfg.precision != PAID_FP64) return fail(nullptr, PAID_EINVAL, "precision mode not built");
+  if (cfg.gram != PAID_GRAM_MFMA) return fail(nullptr, PAID_EINVAL, "gram mode not built");
+  if (cfg.kind < 0 || cfg.kind > 3) return fail(nullptr, PAID_EINVAL, "bad kind");
+  if (cfg.kind == PAID_GAUSS && !(cfg.gauss[2] > 0)) return fail(nullptr, PAID_EINVAL, "gauss width must be > 0");
+  if (cfg.max_regions < 16 || cfg.max_regions > (1L << 28))
+    return fail(nullptr, PAID_EINVAL, "max_regions must be in [16, 2^28]");
+  if (!(cfg.nu >= 0)) return fail(nullptr, PAID_EINVAL, "nu must be >= 0");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(nullptr, PAID_EDEVICE, "no HIP device");
+  if (cfg.device < 0 || cfg.device >= ndev) return fail(nullptr, PAID_EINVAL, "bad device ordinal");
+  e = hipSetDevice(cfg.device);
+  if (e != hipSuccess) return fail(nullptr, PAID_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  paid_ctx *c = new paid_ctx();
+  c->cfg = cfg;
+  if (cfg.stream) {
+    c->stream = (hipStream_t)cfg.stream;
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(nullptr, PAID_EDEVICE, "stream: %s", hipGetErrorString(e));
+    }
+    c->own_stream = true;
+  }
+  e = hipHostMalloc((void **)&c->host_counters, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    paid_destroy(c);
+    return fail(nullptr, PAID_ENOMEM, "pinned counters: %s", hipGetErrorString(e));
+  }
+  if (cfg.profile) {
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+      paid_destroy(c);
+      return fail(nullptr, PAID_EDEVICE, "hipEventCreate failed");
+    }
+  }
+  int rc = ensure_rule(c);
+  if (rc != PAID_OK) {
+    g_create_error = c->err;
+    paid_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return PAID_OK;
+}
+
+void paid_destroy(paid_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->cfg.device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  DevBuf *bufs[] = {&c->entries, &c->tab,  &c->zeta,  &c->svals, &c->ctr,   &c->qv,
+                    &c->ffc,     &c->code, &c->key,   &c->Q,     &c->E,     &c->slot_i,
+                    &c->slot_d,  &c->sel,  &c->dv,    &c->de,    &c->dep,   &c->itau,
+                    &c->errp,    &c->stl,  &c->counters, &c->outs, &c->errs};
+  for (DevBuf *b : bufs) b->release();
+  if (c->host_counters) (void)hipHostFree(c->host_counters);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char *paid_last_error(const paid_ctx *c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const double *q,
+                   int n_q, const double *ff, int n_ff, int ff_L, unsigned channels, double rtol,
+                   double atol, double *out, double *err_out, paid_stats *stats) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if (!params || !q || !ff || !out) return fail(c, PAID_EINVAL, "NULL input or output");
+  if (n_params < 1 || n_q < 1) return fail(c, PAID_EINVAL, "n_params and n_q must be >= 1");
+  if ((channels & ~3u) || !(channels & 3u)) return fail(c, PAID_EINVAL, "channels must be PAID_PP | PAID_PH");
+  if (!(rtol >= 0) || !(atol >= 0) || !(rtol > 0 || atol > 0))
+    return fail(c, PAID_EINVAL, "need rtol > 0 or atol > 0 (both >= 0)");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const paid_config &cfg = c->cfg;
+  std::vector<paid_params> hp;
+  std::vector<double> hq, hff;
+  int rc;
+  if ((rc = to_host(c, params, (size_t)n_params, hp)) != PAID_OK) return rc;
+  if ((rc = to_host(c, q, (size_t)n_q * 2, hq)) != PAID_OK) return rc;
+  int nb = (2 * ff_L + 1) * (2 * ff_L + 1);
+  if (ff_L < 0 || ff_L > kMaxL) return fail(c, PAID_EINVAL, "ff_L must be 0..%d", kMaxL);
+  if (n_ff < 1 || n_ff > nb) return fail(c, PAID_EINVAL, "n_ff must be 1..%d", nb);
+  if ((rc = to_host(c, ff, (size_t)n_ff * nb, hff)) != PAID_OK) return rc;
+  for (double v : hq)
+    if (!isfinite(v)) return fail(c, PAID_EINVAL, "q not finite");
+  if ((rc = check_params(c, hp.data(), n_params, cfg.kind)) != PAID_OK) return rc;
+  int identity = 0;
+  if ((rc = check_ff(c, hff.data(), n_ff, ff_L, identity)) != PAID_OK) return rc;
+
+  const int n_ch = ((channels & 1u) ? 1 : 0) + ((channels & 2u) ? 1 : 0);
+  const int ch_first = (channels & 1u) ? 0 : 1;
+  const long n_ctr_l = (long)n_params * n_q * n_ch;
+  if (n_ctr_l > (1L << 30)) return fail(c, PAID_EINVAL, "too many containers");
+  const int n_ctr = (int)n_ctr_l;
+  const int M = n_ff, MU = M * (M + 1) / 2;
+  const bool store_E = (err_out != nullptr) || cfg.err_mode == PAID_ERR_PER_INTEGRAL;
+
+  // tables and container constants
+  if ((rc = build_tables(c, hp.data(), n_params, cfg.kind)) != PAID_OK) return rc;
+  HIPCHK(c, c->qv.ensure(sizeof(double) * 2 * n_q));
+  HIPCHK(c, hipMemcpyAsync(c->qv.p, hq.data(), sizeof(double) * 2 * n_q, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, c->ffc.ensure(sizeof(double) * n_ff * nb));
+  HIPCHK(c, hipMemcpyAsync(c->ffc.p, hff.data(), sizeof(double) * n_ff * nb, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, c->ctr.ensure(sizeof(Ctr) * n_ctr));
+  HIPCHK(c, launch_container_setup(c->ctr.as<Ctr>(), n_ctr, c->qv.as<double>(), n_q, n_ch, ch_first, c->stream));
+
+  // pool: slots x capacity
+  const long cap = cfg.max_regions;
+  const size_t rec = 16 + 8 * (size_t)MU + (store_E ? 4 * (size_t)MU : 0);
+  size_t pool_bytes;
+  if (cfg.pool_gib > 0) {
+    pool_bytes = (size_t)(cfg.pool_gib * 1073741824.0);
+  } else {
+    size_t fr = 0, tot = 0;
+    HIPCHK(c, hipMemGetInfo(&fr, &tot));
+    pool_bytes = (size_t)(0.55 * (double)(fr + c->code.n + c->key.n + c->Q.n + c->E.n));
+  }
+  long W = cfg.max_active > 0 ? cfg.max_active : (long)(pool_bytes / ((size_t)cap * rec));
+  if (W > n_ctr) W = n_ctr;
+  if (W > 65536) W = 65536;
+  if (W < 1) return fail(c, PAID_ENOMEM, "region pool too small for one container of %ld regions", cap);
+  const int bmax = cfg.batch_max, bmin = cfg.batch;
+  HIPCHK(c, c->code.ensure(sizeof(uint64_t) * W * cap));
+  HIPCHK(c, c->key.ensure(sizeof(double) * W * cap));
+  HIPCHK(c, c->Q.ensure(sizeof(double) * W * cap * MU));
+  if (store_E) HIPCHK(c, c->E.ensure(sizeof(float) * W * cap * MU));
+  HIPCHK(c, c->slot_i.ensure(sizeof(int) * (8 * W + 8)));
+  HIPCHK(c, c->slot_d.ensure(sizeof(double) * (W * (size_t)MU + W)));
+  HIPCHK(c, c->errp.ensure(sizeof(double) * W * (size_t)MU));
+  HIPCHK(c, c->itau.ensure(sizeof(float) * W * (size_t)MU));
+  HIPCHK(c, c->sel.ensure(sizeof(int) * W * (size_t)bmax));
+  HIPCHK(c, c->dv.ensure(sizeof(double) * W * (size_t)bmax * MU));
+  HIPCHK(c, c->de.ensure(sizeof(double) * W * (size_t)bmax));
+  if (store_E) HIPCHK(c, c->dep.ensure(sizeof(double) * W * (size_t)bmax * MU));
+  HIPCHK(c, c->stl.ensure(sizeof(long) * 2 * W));
+  HIPCHK(c, c->counters.ensure(256));
+  const bool out_dev = is_device_ptr(out), err_dev = err_out && is_device_ptr(err_out);
+  const size_t out_bytes = sizeof(double) * (size_t)n_ctr * M * M;
+  if (!out_dev) HIPCHK(c, c->outs.ensure(out_bytes));
+  if (err_out && !err_dev) HIPCHK(c, c->errs.ensure(out_bytes));
+
+  Problem P;
+  memset(&P, 0, sizeof P);
+  P.entries = c->entries.as<Entry>();
+  P.tab = c->tab.as<double>();
+  P.ctr = c->ctr.as<Ctr>();
+  P.n_ctr = n_ctr;
+  P.kind = cfg.kind;
+  P.err_mode = cfg.err_mode;
+  P.precision = cfg.precision;
+  P.gram = cfg.gram;
+  P.gauss_x = cfg.gauss[0];
+  P.gauss_y = cfg.gauss[1];
+  P.gauss_s = cfg.gauss[2];
+  P.rtol = rtol;
+  P.atol = atol;
+  P.nu = cfg.nu;
+  P.L = ff_L;
+  P.nb = 2 * ff_L + 1;
+  P.MB = nb;
+  P.M = M;
+  P.MU = MU;
+  P.ff_identity = identity;
+  P.ffc = c->ffc.as<double>();
+  P.W = (int)W;
+  P.cap = cap;
+  P.bmin = bmin;
+  P.bmax = bmax;
+  P.code = c->code.as<uint64_t>();
+  P.key = c->key.as<double>();
+  P.Q = c->Q.as<double>();
+  P.E = store_E ? c->E.as<float>() : nullptr;
+  int *si = c->slot_i.as<int>();
+  P.cid = si;
+  P.state = si + W;
+  P.nleaf = si + 2 * W;
+  P.selcnt = si + 3 * W;
+  P.flags = si + 4 * W;
+  P.st_depth = si + 5 * W;
+  P.woff = si + 6 * W;  // W + 1 entries
+  P.sel = c->sel.as<int>();
+  P.val = c->slot_d.as<double>();
+  P.err = c->slot_d.as<double>() + W * (size_t)MU;
+  P.errp = store_E ? c->errp.as<double>() : nullptr;
+  P.itau = c->itau.as<float>();
+  P.dv = c->dv.as<double>();
+  P.de = c->de.as<double>();
+  P.dep = store_E ? c->dep.as<double>() : nullptr;
+  P.st_rounds = c->stl.as<long>();
+  P.st_splits = c->stl.as<long>() + W;
+  int *cnt = c->counters.as<int>();
+  P.qhead = cnt;            // [0]
+  P.counters = cnt + 4;     // [4..7]: done, not converged, work items
+  P.gstats = reinterpret_cast<long long *>(cnt + 16);  // [16..23]
+  P.out = out_dev ? out : c->outs.as<double>();
+  P.err_out = err_out ? (err_dev ? err_out : c->errs.as<double>()) : nullptr;
+
+  HIPCHK(c, hipMemsetAsync(c->slot_i.p, 0, sizeof(int) * (8 * W + 8), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->counters.p, 0, 256, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->stl.p, 0, sizeof(long) * 2 * W, c->stream));
+
+  int dev_cus = 256;
+  {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, cfg.device) == hipSuccess && v > 0)
+      dev_cus = v;
+  }
+  const int eval_grid = dev_cus * 16;
+  long rounds = 0, eval_items = 0;
+  double eval_ms = 0.0;
+  for (;;) {
+    HIPCHK(c, launch_admit(P, c->stream));
+    HIPCHK(c, launch_root(P, c->stream));
+    HIPCHK(c, launch_select(P, c->stream));
+    HIPCHK(c, launch_worklist(P, c->stream));
+    if (cfg.profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCHK(c, launch_eval(P, eval_grid, c->stream));
+    if (cfg.profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCHK(c, launch_update(P, c->stream));
+    HIPCHK(c, launch_finalize(P, c->stream));
+    ++rounds;
+    HIPCHK(c, hipMemcpyAsync(c->host_counters, cnt + 4, 12, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    eval_items += c->host_counters[2];
+    if (cfg.profile) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      eval_ms += ms;
+    }
+    if (c->host_counters[0] >= n_ctr) break;
+    if (rounds > 4L * cap + 64L * (n_ctr / W + 1))
+      return fail(c, PAID_EINTERNAL, "round loop did not finish (%ld rounds)", rounds);
+  }
+  if (!out_dev) HIPCHK(c, hipMemcpyAsync(out, c->outs.p, out_bytes, hipMemcpyDeviceToHost, c->stream));
+  if (err_out && !err_dev)
+    HIPCHK(c, hipMemcpyAsync(err_out, c->errs.p, out_bytes, hipMemcpyDeviceToHost, c->stream));
+  long long gs[4] = {0, 0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(gs, P.gstats, sizeof gs, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int notconv = c->host_counters[1];
+  if (stats) {
+    memset(stats, 0, sizeof *stats);
+    stats->containers = n_ctr;
+    stats->not_converged = notconv;
+    stats->rounds = gs[0];
+    stats->splits = gs[1];
+    stats->regions = gs[2];
+    stats->max_depth = (int)gs[3];
+    stats->kernel_evals = 81L * n_ctr + 289L * gs[1];
+    stats->launch_rounds = rounds;
+    stats->max_active = (int)W;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->eval_seconds = eval_ms * 1e-3;
+    stats->eval_launches = cfg.profile ? rounds : 0;
+    stats->eval_items = eval_items;
+  }
+  return notconv ? PAID_ENOCONV : PAID_OK;
+}
+
+int paid_kernel_eval(paid_ctx *c, const paid_params *p, unsigned channel, const double *a,
+                     const double *b, int n, double *out) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if (!p || !a || !b || !out || n < 0) return fail(c, PAID_EINVAL, "bad arguments");
+  if (channel != PAID_PP && channel != PAID_PH) return fail(c, PAID_EINVAL, "channel must be PAID_PP or PAID_PH");
+  if (c->cfg.kind > 1) return fail(c, PAID_EINVAL, "kernel_eval needs a bubble kind");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  std::vector<paid_params> hp;
+  std::vector<double> ha, hb;
+  int rc;
+  if ((rc = to_host(c, p, 1, hp)) != PAID_OK) return rc;
+  if ((rc = check_params(c, hp.data(), 1, c->cfg.kind)) != PAID_OK) return rc;
+  if (n == 0) return PAID_OK;
+  if ((rc = to_host(c, a, (size_t)n, ha)) != PAID_OK) return rc;
+  if ((rc = to_host(c, b, (size_t)n, hb)) != PAID_OK) return rc;
+  double emax = 4.0 * fabs(hp[0].t) + 4.0 * fabs(hp[0].tp) + fabs(hp[0].mu);
+  for (int i = 0; i < n; ++i)
+    if (!(fabs(ha[i]) <= emax && fabs(hb[i]) <= emax))
+      return fail(c, PAID_EINVAL, "energy %d outside the dispersion range +-%g", i, emax);
+  if ((rc = build_tables(c, hp.data(), 1, c->cfg.kind)) != PAID_OK) return rc;
+  DevBuf tmp;
+  HIPCHK(c, tmp.ensure(sizeof(double) * 3 * (size_t)n));
+  double *da = tmp.as<double>(), *db = da + n, *dout = db + n;
+  HIPCHK(c, hipMemcpyAsync(da, ha.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(db, hb.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_kernel_eval(c->entries.as<Entry>(), c->tab.as<double>(), channel == PAID_PH ? 1 : 0,
+                               da, db, n, dout, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, dout, sizeof(double) * n, hipMemcpyDefault, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  tmp.release();
+  return PAID_OK;
+}
+
+int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsigned channel,
+                       const double *ff, int n_ff, int ff_L, const int *codes, int n, double *q2n,
+                       double *err) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if (!p || !l || !ff || !codes || !q2n || !err || n < 1)
+    return fail(c, PAID_EINVAL, "bad arguments");
+  if (channel != PAID_PP && channel != PAID_PH) return fail(c, PAID_EINVAL, "channel must be PAID_PP or PAID_PH");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const paid_config &cfg = c->cfg;
+  std::vector<paid_params> hp;
+  std::vector<double> hl, hff;
+  std::vector<int> hc;
+  int rc;
+  if ((rc = to_host(c, p, 1, hp)) != PAID_OK) return rc;
+  if ((rc = check_params(c, hp.data(), 1, cfg.kind)) != PAID_OK) return rc;
+  if ((rc = to_host(c, l, 2, hl)) != PAID_OK) return rc;
+  if (ff_L < 0 || ff_L > kMaxL) return fail(c, PAID_EINVAL, "ff_L must be 0..%d", kMaxL);
+  int nb = (2 * ff_L + 1) * (2 * ff_L + 1);
+  if (n_ff < 1 || n_ff > nb) return fail(c, PAID_EINVAL, "n_ff must be 1..%d", nb);
+  if ((rc = to_host(c, ff, (size_t)n_ff * nb, hff)) != PAID_OK) return rc;
+  int identity = 0;
+  if ((rc = check_ff(c, hff.data(), n_ff, ff_L, identity)) != PAID_OK) return rc;
+  if ((rc = to_host(c, codes, (size_t)n * 3, hc)) != PAID_OK) return rc;
+  std::vector<uint64_t> pc(n);
+  for (int i = 0; i < n; ++i) {
+    int d = hc[3 * i], ix = hc[3 * i + 1], iy = hc[3 * i + 2];
+    if (d < 0 || d > 26 || ix < 0 || iy < 0 || ix >= (1 << d) || iy >= (1 << d))
+      return fail(c, PAID_EINVAL, "bad rectangle code %d", i);
+    pc[i] = make_code(d, (uint64_t)ix, (uint64_t)iy);
+  }
+  if ((rc = build_tables(c, hp.data(), 1, cfg.kind)) != PAID_OK) return rc;
+  HIPCHK(c, c->qv.ensure(sizeof(double) * 2));
+  HIPCHK(c, hipMemcpyAsync(c->qv.p, hl.data(), sizeof(double) * 2, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, c->ffc.ensure(sizeof(double) * n_ff * nb));
+  HIPCHK(c, hipMemcpyAsync(c->ffc.p, hff.data(), sizeof(double) * n_ff * nb, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, c->ctr.ensure(sizeof(Ctr)));
+  HIPCHK(c, launch_container_setup(c->ctr.as<Ctr>(), 1, c->qv.as<double>(), 1, 1,
+                                   channel == PAID_PH ? 1 : 0, c->stream));
+  const int M = n_ff, MU = M * (M + 1) / 2;
+  const long cap = 4L * n;
+  DevBuf code, key, Q, si, dv, de, itau, cnt, ctrid;
+  HIPCHK(c, code.ensure(sizeof(uint64_t) * cap));
+  HIPCHK(c, key.ensure(sizeof(double) * cap));
+  HIPCHK(c, Q.ensure(sizeof(double) * cap * MU));
+  HIPCHK(c, si.ensure(sizeof(int) * (8 + (size_t)n)));
+  HIPCHK(c, dv.ensure(sizeof(double) * (size_t)n * MU));
+  HIPCHK(c, de.ensure(sizeof(double) * (size_t)n));
+  HIPCHK(c, itau.ensure(sizeof(float) * MU));
+  HIPCHK(c, cnt.ensure(256));
+  HIPCHK(c, hipMemsetAsync(Q.p, 0, sizeof(double) * cap * MU, c->stream));
+  HIPCHK(c, hipMemsetAsync(key.p, 0, sizeof(double) * cap, c->stream));
+  HIPCHK(c, hipMemcpyAsync(code.p, pc.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, c->stream));
+  // slot state: cid 0, state active, nleaf n, selcnt n, woff {0, n}, flags, depth; sel = 0..n-1
+  std::vector<int> hs(8 + (size_t)n, 0);
+  hs[0] = 0;      // cid
+  hs[1] = SLOT_ACTIVE;
+  hs[2] = n;      // nleaf
+  hs[3] = n;      // selcnt
+  hs[4] = 0;      // flags
+  hs[5] = 0;      // depth
+  hs[6] = 0;      // woff[0]
+  hs[7] = n;      // woff[1]
+  for (int i = 0; i < n; ++i) hs[8 + i] = i;
+  HIPCHK(c, hipMemcpyAsync(si.p, hs.data(), sizeof(int) * hs.size(), hipMemcpyHostToDevice, c->stream));
+  int hcnt[64] = {0};
+  hcnt[4 + 2] = n;  // counters[2]: work items
+  HIPCHK(c, hipMemcpyAsync(cnt.p, hcnt, sizeof hcnt, hipMemcpyHostToDevice, c->stream));
+  Problem P;
+  memset(&P, 0, sizeof P);
+  P.entries = c->entries.as<Entry>();
+  P.tab = c->tab.as<double>();
+  P.ctr = c->ctr.as<Ctr>();
+  P.n_ctr = 1;
+  P.kind = cfg.kind;
+  P.err_mode = PAID_ERR_GLOBAL;
+  P.gauss_x = cfg.gauss[0];
+  P.gauss_y = cfg.gauss[1];
+  P.gauss_s = cfg.gauss[2];
+  P.L = ff_L;
+  P.nb = 2 * ff_L + 1;
+  P.MB = nb;
+  P.M = M;
+  P.MU = MU;
+  P.ff_identity = identity;
+  P.ffc = c->ffc.as<double>();
+  P.W = 1;
+  P.cap = cap;
+  P.bmin = 1;
+  P.bmax = n;
+  P.code = code.as<uint64_t>();
+  P.key = key.as<double>();
+  P.Q = Q.as<double>();
+  int *s = si.as<int>();
+  P.cid = s;
+  P.state = s + 1;
+  P.nleaf = s + 2;
+  P.selcnt = s + 3;
+  P.flags = s + 4;
+  P.st_depth = s + 5;
+  P.woff = s + 6;
+  P.sel = s + 8;
+  P.itau = itau.as<float>();
+  P.dv = dv.as<double>();
+  P.de = de.as<double>();
+  P.counters = cnt.as<int>() + 4;
+  HIPCHK(c, launch_eval(P, n < 4096 ? n : 4096, c->stream));
+  std::vector<double> hQ((size_t)cap * MU), hk(cap);
+  HIPCHK(c, hipMemcpyAsync(hQ.data(), Q.p, sizeof(double) * cap * MU, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(hk.data(), key.p, sizeof(double) * cap, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<double> oq((size_t)n * 4 * MU), oe((size_t)n * 4);
+  for (int r = 0; r < n; ++r)
+    for (int ch = 0; ch < 4; ++ch) {
+      long ri = ch == 0 ? r : n + 3L * r + (ch - 1);
+      memcpy(&oq[((size_t)r * 4 + ch) * MU], &hQ[ri * MU], sizeof(double) * MU);
+      oe[(size_t)r * 4 + ch] = hk[ri];
+    }
+  HIPCHK(c, hipMemcpy(q2n, oq.data(), sizeof(double) * oq.size(), hipMemcpyDefault));
+  HIPCHK(c, hipMemcpy(err, oe.data(), sizeof(double) * oe.size(), hipMemcpyDefault));
+  return PAID_OK;
+}
+
+}  // extern "C"

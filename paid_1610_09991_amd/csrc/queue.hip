@@ -1,0 +1,440 @@
+// queue.hip -- the task container of Alg. 2 on the device: admission of
+// containers into resident slots, worst-error-first bulk extraction, the
+// flattened work list, the error/value updates and the final sums.
+//
+// Paper correspondence (Sec. 4): the heap keyed on the error becomes, per
+// container, a histogram of the leaf keys (4 bins per octave) from which the
+// largest keys are taken in order; Listing 2's MaxTask extraction becomes a
+// per-round count that is at least `bmin`, covers every leaf whose key alone
+// exceeds the tolerance (those must be split before the container can
+// converge), and covers the error deficit ERR - eps; Listing 4's update
+// (ERR -= parent, += children) is a fixed-order FP64 sum of per-parent
+// deltas; the termination test of Listing 5 is re-checked on sums recomputed
+// from the leaves before it is accepted.
+#include <math.h>
+
+#include "launch.h"
+
+namespace paid {
+
+namespace {
+
+constexpr int kBins = 512;
+constexpr int kSelThreads = 256;
+
+__device__ inline double block_sum(double v, double *sh) {
+  // fixed-order reduction: deterministic for a fixed block size
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (t < o) sh[t] += sh[t + o];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double block_max(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (t < o) sh[t] = fmax(sh[t], sh[t + o]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// exclusive block prefix of an int flag/count; returns the block total
+__device__ inline int block_scan(int v, int *sh, int &excl) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    if (w < wv) before += sh[w];
+    tot += sh[w];
+  }
+  excl = before + x - v;
+  __syncthreads();
+  return tot;
+}
+
+// Sum over the leaves of a slot, in a fixed order, of Q (into val) and of
+// the per-pair errors (into errp, when stored); returns the sum of the keys.
+__device__ double resum_leaves(const Problem &P, int s, double *shd) {
+  const int t = threadIdx.x, lane = t & 63, grp = t >> 6, ng = blockDim.x >> 6;
+  const long n = P.nleaf[s], base = (long)s * P.cap;
+  for (int c0 = 0; c0 < P.MU; c0 += 64) {
+    int pid = c0 + lane;
+    double aq = 0.0, ae = 0.0;
+    if (pid < P.MU) {
+      for (long i = grp; i < n; i += ng) {
+        aq += P.Q[(base + i) * P.MU + pid];
+        if (P.E) ae += (double)P.E[(base + i) * P.MU + pid];
+      }
+    }
+    shd[t] = aq;
+    shd[blockDim.x + t] = ae;
+    __syncthreads();
+    if (grp == 0 && pid < P.MU) {
+      double sq = 0.0, se = 0.0;
+      for (int g = 0; g < ng; ++g) {
+        sq += shd[g * 64 + lane];
+        se += shd[blockDim.x + g * 64 + lane];
+      }
+      P.val[(long)s * P.MU + pid] = sq;
+      if (P.errp) P.errp[(long)s * P.MU + pid] = se;
+    }
+    __syncthreads();
+  }
+  double ks = 0.0;
+  for (long i = t; i < n; i += blockDim.x) ks += P.key[base + i];
+  double k = block_sum(ks, shd);
+  if (t == 0) P.err[s] = k;
+  __syncthreads();
+  return k;
+}
+
+// tolerance; returns 1 if the termination test passes.  In the per-integral
+// mode also refreshes the key weights 1/tau used for new children.
+__device__ int tolerance_test(const Problem &P, int s, double *shd, double &eps, double &deficit) {
+  const int t = threadIdx.x;
+  double a = 0.0, mx = 0.0;
+  for (int pid = t; pid < P.MU; pid += blockDim.x) {
+    double v = fabs(P.val[(long)s * P.MU + pid]);
+    a += v;
+    mx = fmax(mx, v);
+  }
+  double l1 = block_sum(a, shd), vmax = block_max(mx, shd);
+  if (P.err_mode == 0) {
+    eps = fmax(P.atol, P.rtol * l1);
+    double E = P.err[s];
+    deficit = E - eps;
+    return E <= eps;
+  }
+  // per integral: every pair within its own tolerance; deficit in tau units
+  double ex = 0.0;
+  int bad = 0;
+  for (int pid = t; pid < P.MU; pid += blockDim.x) {
+    double v = fabs(P.val[(long)s * P.MU + pid]);
+    double tau = fmax(P.atol, P.rtol * fmax(v, P.nu * vmax));
+    double e = P.errp[(long)s * P.MU + pid];
+    if (e > tau) {
+      bad = 1;
+      ex += (e - tau) / tau;
+    }
+    P.itau[(long)s * P.MU + pid] = (float)(tau > 0.0 ? 1.0 / tau : 0.0);
+  }
+  double excess = block_sum(ex, shd);
+  double nbad = block_sum((double)bad, shd);
+  eps = 0.0;
+  deficit = excess;
+  return nbad == 0.0;
+}
+
+__device__ inline int key_bin(double k, int emax_bits) {
+  if (!(k > 0.0)) return kBins - 1;
+  int b = emax_bits - (int)(__double_as_longlong(k) >> 50);
+  return b < 0 ? 0 : (b > kBins - 1 ? kBins - 1 : b);
+}
+
+__global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
+  __shared__ double shd[2 * kSelThreads];
+  __shared__ int shi[kSelThreads];
+  __shared__ unsigned int hcnt[kBins];
+  __shared__ unsigned long long hsum[kBins];
+  __shared__ int s_bfull, s_bpart, s_part, s_k;
+  const int s = blockIdx.x, t = threadIdx.x;
+  if (s >= P.W) return;
+  if (P.state[s] != SLOT_ACTIVE) {
+    if (t == 0) P.selcnt[s] = 0;
+    return;
+  }
+  double eps, deficit;
+  int conv = tolerance_test(P, s, shd, eps, deficit);
+  if (conv) {  // accept only on sums recomputed from the leaves
+    resum_leaves(P, s, shd);
+    conv = tolerance_test(P, s, shd, eps, deficit);
+    if (conv) {
+      if (t == 0) {
+        P.selcnt[s] = 0;
+        P.flags[s] |= 1;
+        P.state[s] = SLOT_DONE;
+      }
+      return;
+    }
+  }
+  const long n = P.nleaf[s], base = (long)s * P.cap;
+  if (n + 3 > P.cap) {
+    if (t == 0) {
+      P.selcnt[s] = 0;
+      P.flags[s] |= 2;
+      P.state[s] = SLOT_DONE;
+    }
+    return;
+  }
+  long kmaxl = (P.cap - n) / 3;
+  if (kmaxl > P.bmax) kmaxl = P.bmax;
+  if (kmaxl > n) kmaxl = n;
+  const int kmax = (int)kmaxl;
+  // pass 1: largest key
+  double mk = 0.0;
+  for (long i = t; i < n; i += blockDim.x) mk = fmax(mk, P.key[base + i]);
+  const double maxkey = block_max(mk, shd);
+  const int eb = (int)(__double_as_longlong(maxkey > 0.0 ? maxkey : 1.0) >> 50);
+  // pass 2: histogram of counts and fixed-point sums (exact, order-free)
+  for (int b = t; b < kBins; b += blockDim.x) {
+    hcnt[b] = 0u;
+    hsum[b] = 0ull;
+  }
+  __syncthreads();
+  const double scale = maxkey > 0.0 ? 1099511627776.0 / maxkey : 0.0;  // 2^40 / maxkey
+  for (long i = t; i < n; i += blockDim.x) {
+    double k = P.key[base + i];
+    int b = key_bin(k, eb);
+    atomicAdd(&hcnt[b], 1u);
+    atomicAdd(&hsum[b], (unsigned long long)(k * scale));
+  }
+  __syncthreads();
+  if (t < 64) {  // one wave scans the bins: 8 per lane
+    const int lane = t;
+    unsigned int c8 = 0;
+    unsigned long long s8 = 0;
+    for (int j = 0; j < 8; ++j) {
+      c8 += hcnt[lane * 8 + j];
+      s8 += hsum[lane * 8 + j];
+    }
+    unsigned int cinc = c8;
+    unsigned long long sinc = s8;
+    for (int o = 1; o < 64; o <<= 1) {
+      unsigned int yc = __shfl_up(cinc, o, 64);
+      unsigned long long ys = __shfl_up(sinc, o, 64);
+      if (lane >= o) {
+        cinc += yc;
+        sinc += ys;
+      }
+    }
+    unsigned int cex = cinc - c8;
+    unsigned long long sex = sinc - s8;
+    double dd = deficit * scale;
+    unsigned long long dfix = dd >= 4.0e18 ? 4000000000000000000ull : (unsigned long long)(dd > 0 ? dd : 0.0);
+    int beps = (P.err_mode == 0) ? key_bin(eps, eb) : 0;
+    if (P.err_mode == 0 && eps >= maxkey) beps = -1;  // no single leaf exceeds eps
+    // first bin b (in this lane's 8) meeting all conditions
+    int found = kBins, fcnt = 0;
+    unsigned int cc = cex;
+    unsigned long long ss = sex;
+    for (int j = 0; j < 8; ++j) {
+      int b = lane * 8 + j;
+      cc += hcnt[b];
+      ss += hsum[b];
+      if (found == kBins && ss >= dfix && b >= beps && (int)cc >= P.bmin) {
+        found = b;
+        fcnt = (int)cc;
+      }
+    }
+    // smallest lane with a hit
+    int best = found;
+    for (int o = 32; o >= 1; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+    int bcnt = (found == best) ? fcnt : 0;
+    for (int o = 32; o >= 1; o >>= 1) bcnt = max(bcnt, __shfl_xor(bcnt, o, 64));
+    if (best == kBins) { best = kBins - 1; bcnt = (int)n; }
+    int k = bcnt < kmax ? bcnt : kmax;
+    // whole bins up to bfull, then `part` leaves of bin bfull+1 in index order
+    int bfull = best, part = 0;
+    if (bcnt > kmax) {
+      // largest b with cumulative count <= kmax
+      int lastb = -1;
+      unsigned int c2 = cex;
+      for (int j = 0; j < 8; ++j) {
+        int b = lane * 8 + j;
+        c2 += hcnt[b];
+        if ((int)c2 <= kmax) lastb = b;
+      }
+      for (int o = 32; o >= 1; o >>= 1) lastb = max(lastb, __shfl_xor(lastb, o, 64));
+      bfull = lastb;
+      int cnt_full = 0;
+      // cumulative count through bfull
+      unsigned int c3 = cex;
+      int mine = -1;
+      for (int j = 0; j < 8; ++j) {
+        int b = lane * 8 + j;
+        c3 += hcnt[b];
+        if (b == bfull) mine = (int)c3;
+      }
+      for (int o = 32; o >= 1; o >>= 1) mine = max(mine, __shfl_xor(mine, o, 64));
+      cnt_full = bfull >= 0 ? mine : 0;
+      part = kmax - cnt_full;
+    }
+    if (lane == 0) {
+      s_bfull = bfull;
+      s_bpart = bfull + 1;
+      s_part = part;
+      s_k = k;
+    }
+  }
+  __syncthreads();
+  const int bfull = s_bfull, bpart = s_bpart, part = s_part;
+  // pass 3: order-preserving compaction
+  int out = 0, seenpart = 0;
+  int *sel = P.sel + (long)s * P.bmax;
+  for (long b0 = 0; b0 < n; b0 += blockDim.x) {
+    long i = b0 + t;
+    int bin = (i < n) ? key_bin(P.key[base + i], eb) : kBins;
+    int isp = (i < n && bin == bpart) ? 1 : 0, ex1;
+    int totp = block_scan(isp, shi, ex1);
+    int flag = (i < n) && (bin <= bfull || (isp && seenpart + ex1 < part));
+    int ex2;
+    int totf = block_scan(flag, shi, ex2);
+    if (flag && out + ex2 < s_k) sel[out + ex2] = (int)i;
+    out += totf;
+    seenpart += totp;
+    if (out >= s_k) break;
+  }
+  if (t == 0) P.selcnt[s] = out < s_k ? out : s_k;
+}
+
+__global__ void k_worklist(Problem P) {
+  __shared__ int shi[1024];
+  const int t = threadIdx.x;
+  int carry = 0;
+  for (int b0 = 0; b0 < P.W; b0 += blockDim.x) {
+    int s = b0 + t, v = (s < P.W) ? P.selcnt[s] : 0, ex;
+    int tot = block_scan(v, shi, ex);
+    if (s < P.W) P.woff[s] = carry + ex;
+    carry += tot;
+  }
+  if (t == 0) {
+    P.woff[P.W] = carry;
+    P.counters[2] = carry;
+  }
+}
+
+// Container admission: empty slots take the next containers in slot order.
+__global__ void k_admit(Problem P) {
+  __shared__ int shi[1024];
+  __shared__ int s_head;
+  const int t = threadIdx.x;
+  if (t == 0) s_head = *P.qhead;
+  __syncthreads();
+  if (s_head >= P.n_ctr) return;
+  int head = s_head;
+  for (int b0 = 0; b0 < P.W; b0 += blockDim.x) {
+    int s = b0 + t, e = (s < P.W && P.state[s] == SLOT_EMPTY) ? 1 : 0, ex;
+    int tot = block_scan(e, shi, ex);
+    if (e && head + ex < P.n_ctr) {
+      P.cid[s] = head + ex;
+      P.state[s] = SLOT_NEW;
+    }
+    head += tot;
+  }
+  if (t == 0) *P.qhead = head < P.n_ctr ? head : P.n_ctr;
+}
+
+__global__ void __launch_bounds__(kSelThreads) k_update(Problem P) {
+  __shared__ double shd[2 * kSelThreads];
+  const int s = blockIdx.x, t = threadIdx.x;
+  if (s >= P.W) return;
+  const int k = P.selcnt[s];
+  if (k == 0) return;
+  const int lane = t & 63, grp = t >> 6, ng = blockDim.x >> 6;
+  const long it0 = (long)s * P.bmax;
+  for (int c0 = 0; c0 < P.MU; c0 += 64) {
+    int pid = c0 + lane;
+    double av = 0.0, ap = 0.0;
+    if (pid < P.MU)
+      for (int r = grp; r < k; r += ng) {
+        av += P.dv[(it0 + r) * P.MU + pid];
+        if (P.dep) ap += P.dep[(it0 + r) * P.MU + pid];
+      }
+    shd[t] = av;
+    shd[blockDim.x + t] = ap;
+    __syncthreads();
+    if (grp == 0 && pid < P.MU) {
+      double sv = 0.0, sp = 0.0;
+      for (int g = 0; g < ng; ++g) {
+        sv += shd[g * 64 + lane];
+        sp += shd[blockDim.x + g * 64 + lane];
+      }
+      P.val[(long)s * P.MU + pid] += sv;
+      if (P.errp) P.errp[(long)s * P.MU + pid] += sp;
+    }
+    __syncthreads();
+  }
+  double de = 0.0;
+  for (int r = t; r < k; r += blockDim.x) de += P.de[it0 + r];
+  double d = block_sum(de, shd);
+  if (t == 0) {
+    P.err[s] += d;
+    P.nleaf[s] += 3 * k;
+    P.st_rounds[s] += 1;
+    P.st_splits[s] += k;
+  }
+}
+
+__global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
+  __shared__ double shd[2 * kSelThreads];
+  const int s = blockIdx.x, t = threadIdx.x;
+  if (s >= P.W || P.state[s] != SLOT_DONE) return;
+  if (P.flags[s] & 2) resum_leaves(P, s, shd);  // budget exit: sums from the leaves
+  const long c = P.cid[s];
+  const int M = P.M;
+  for (int pid = t; pid < P.MU; pid += blockDim.x) {
+    int p = 0, k = pid;
+    while (k >= M - p) { k -= M - p; ++p; }
+    int q = p + k;
+    double v = P.val[(long)s * P.MU + pid];
+    P.out[c * M * M + p * M + q] = v;
+    P.out[c * M * M + q * M + p] = v;
+    if (P.err_out) {
+      double e = P.errp[(long)s * P.MU + pid];
+      P.err_out[c * M * M + p * M + q] = e;
+      P.err_out[c * M * M + q * M + p] = e;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    atomicAdd(&P.counters[0], 1);
+    if (P.flags[s] & 2) atomicAdd(&P.counters[1], 1);
+    atomicAdd((unsigned long long *)&P.gstats[0], (unsigned long long)P.st_rounds[s]);
+    atomicAdd((unsigned long long *)&P.gstats[1], (unsigned long long)P.st_splits[s]);
+    atomicAdd((unsigned long long *)&P.gstats[2], (unsigned long long)P.nleaf[s]);
+    atomicMax((unsigned long long *)&P.gstats[3], (unsigned long long)P.st_depth[s]);
+    P.state[s] = SLOT_EMPTY;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_admit(const Problem &p, hipStream_t s) {
+  hipLaunchKernelGGL(k_admit, dim3(1), dim3(1024), 0, s, p);
+  return hipGetLastError();
+}
+hipError_t launch_select(const Problem &p, hipStream_t s) {
+  hipLaunchKernelGGL(k_select, dim3(p.W), dim3(kSelThreads), 0, s, p);
+  return hipGetLastError();
+}
+hipError_t launch_worklist(const Problem &p, hipStream_t s) {
+  hipLaunchKernelGGL(k_worklist, dim3(1), dim3(1024), 0, s, p);
+  return hipGetLastError();
+}
+hipError_t launch_update(const Problem &p, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(p.W), dim3(kSelThreads), 0, s, p);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(const Problem &p, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(p.W), dim3(kSelThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace paid

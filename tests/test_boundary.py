@@ -1,0 +1,39 @@
+"""The C ABI: the library loads and exports every function include/paid.h
+declares (no device needed; no compute call is made)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "paid.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(paid_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("paid_create", "paid_integrate", "paid_destroy", "paid_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paid_1610_09991_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paid_1610_09991_amd import build
+        build.build()
+    L = P.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+    assert set(P.EXPORTS) == set(declared_functions())
+
+
+def test_binding_refuses_to_run_without_the_library(tmp_path, monkeypatch):
+    import paid_1610_09991_amd as P
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(P, "_lib", None)
+    with pytest.raises(RuntimeError):
+        P.Context()

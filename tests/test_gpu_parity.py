@@ -1,0 +1,248 @@
+"""GPU parity: libpaid (HIP, gfx950) against the FP64 CPU oracle, through the
+C ABI.  Gate for floating point (per integral, same seeded inputs):
+    |gpu_pq - ref_pq| <= rtol * max(|ref_pq|, nu * max |ref|),  nu = 1e-3,
+with ref the oracle at rtol/1000.  Kernel and rectangle values are compared
+element by element at rounding level."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NU = 1e-3
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paid_1610_09991_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def ctx(P):
+    c = P.Context(max_regions=1 << 16, max_active=512)
+    yield c
+    c.close()
+
+
+def gate_ratio(gpu, ref, rtol):
+    scale = np.maximum(np.abs(ref), NU * np.abs(ref).max())
+    return float((np.abs(gpu - ref) / (rtol * scale)).max())
+
+
+def oracle_refs(cfg, picks, rtol):
+    """oracle values for (param index, q index, channel) picks"""
+    conts = []
+    for ip, iq, ch in picks:
+        p = cfg["params"][ip]
+        conts.append(O.Container(cfg["ff"], cfg["L"], t=p[0], tp=p[1], mu=p[2], T=p[3],
+                                 Omega=p[4], lx=cfg["q"][iq][0], ly=cfg["q"][iq][1],
+                                 channel=ch))
+    vals, _, _, nc = O.integrate_batch(conts, rtol=rtol, err_mode=O.ERR_GLOBAL, batch=4,
+                                       nthreads=THREADS)
+    assert nc == 0
+    return vals
+
+
+# ------------------------------------------------------------------ kernel
+def adversarial(Om, T, emax):
+    pts = []
+    for k in (1, 3, 6, 9, 12, 15):
+        d = 10.0 ** -k
+        pts += [(Om * (1 + d), Om * (1 - d)), (Om * (1 + d), -Om), (-Om * (1 - d), Om),
+                (0.37 * (1 + d), 0.37), (0.37 * (1 + d), -0.37), (d * T, -2 * d * T),
+                (-1.3 * (1 + d), -1.3), (3.1, 3.1 * (1 - d))]
+    pts += [(0.0, 0.0), (emax * 0.999, -emax * 0.999), (emax * 0.999, emax * 0.998)]
+    rng = np.random.default_rng(7)
+    pts += [tuple(x) for x in rng.uniform(-emax * 0.99, emax * 0.99, (40, 2))]
+    return [(a, b) for a, b in pts if abs(a) <= emax and abs(b) <= emax]
+
+
+@pytest.mark.parametrize("T,Om", [(0.005, 0.01), (0.01, 0.1), (0.1, 1.0), (0.01, 10.0),
+                                  (0.05, 0.0)])
+def test_kernel_matches_oracle_at_rounding_level(ctx, P, T, Om):
+    row = (1.0, -0.25, -0.95, T, Om)
+    emax = 4 + 1 + 0.95
+    pts = adversarial(max(Om, 1e-3), T, emax)
+    a = np.array([p[0] for p in pts])
+    b = np.array([p[1] for p in pts])
+    for ch, och in ((P.PH, O.PH), (P.PP, O.PP)):
+        g = ctx.kernel(row, a, b, ch)
+        for x, y, v in zip(a, b, g):
+            ref = O.kernel(x, y, Om, T, och)
+            loc = abs(O.kernel(abs(x) + 0.5 * T, abs(x) + 0.5 * T, Om, T, O.PH))
+            assert abs(v - ref) <= 2e-12 * max(abs(ref), loc), (ch, x, y, v, ref)
+
+
+def test_kernel_rejects_energies_outside_the_band(ctx, P):
+    with pytest.raises(P.PaidError):
+        ctx.kernel((1.0, 0.0, 0.0, 0.1, 0.1), [4.5], [0.0])
+
+
+# ------------------------------------------------------------------ rectangles
+@pytest.mark.parametrize("ff_name", ["ff9", "ff5", "ff25", "ff1"])
+@pytest.mark.parametrize("ch", ["pp", "ph"])
+def test_children_match_oracle_rectangles(ctx, P, ff_name, ch):
+    ff, L = {"ff9": (W.ff_box(1), 1), "ff5": (W.ff5(), 1), "ff25": (W.ff_box(2), 2),
+             "ff1": (W.ff_box(0), 0)}[ff_name]
+    pch, och = (P.PP, O.PP) if ch == "pp" else (P.PH, O.PH)
+    row = (1.0, -0.3, -1.1, 0.02, 0.05)
+    l = (2.88, 0.26)
+    rng = np.random.default_rng(3)
+    codes = [(0, 0, 0), (1, 1, 0), (2, 3, 1)]
+    for d in (4, 7, 11):
+        for _ in range(3):
+            codes.append((d, int(rng.integers(0, 2 ** d)), int(rng.integers(0, 2 ** d))))
+    codes = np.array(codes)
+    q2n, keys = ctx.children(row, l, pch, ff, L, codes)
+    c = O.Container(ff, L, t=row[0], tp=row[1], mu=row[2], T=row[3], Omega=row[4], lx=l[0],
+                    ly=l[1], channel=och)
+    for i, (d, ix, iy) in enumerate(codes):
+        w = 2 * math.pi / 2 ** d
+        for k in range(4):
+            cx, cy = k & 1, k >> 1
+            x0 = -math.pi + ix * w + cx * w / 2
+            y0 = -math.pi + iy * w + cy * w / 2
+            qn, ref = c.region(x0, x0 + w / 2, y0, y0 + w / 2)
+            big = np.abs(ref).max() + 1e-300
+            assert np.abs(q2n[i, k] - ref).max() <= 1e-12 * big, (i, k)
+            # error of the pair: same quantity, different rounding order
+            ek = np.abs(qn - ref).sum()
+            assert abs(keys[i, k] - ek) <= 1e-12 * np.abs(ref).sum() + 1e-7 * ek, (i, k)
+
+
+# ------------------------------------------------------------------ full integrations
+def test_c1_full_workload(ctx, P):
+    """8x8 q, FF5, pp+ph at the workload's rtol 1e-4 and at 1e-6."""
+    cfg = W.config("C1")
+    picks = W.containers(cfg)
+    ref = oracle_refs(cfg, picks, 1e-10)
+    for rtol in (1e-4, 1e-6):
+        out, _, st, rc = ctx.integrate(cfg["params"], cfg["q"], cfg["ff"], cfg["L"], rtol=rtol)
+        assert rc == P.OK and st["not_converged"] == 0
+        for k, (ip, iq, ch) in enumerate(picks):
+            assert gate_ratio(out[ip, iq, ch], ref[k], rtol) <= 1.0, (rtol, ip, iq, ch)
+            assert np.array_equal(out[ip, iq, ch], out[ip, iq, ch].T)
+
+
+def test_batched_random_parameter_sets(ctx, P):
+    """Uneven refinement depths in one call: random (mu, T, t', Omega) rows."""
+    p = W.random_params(6, seed=3, omega_range=(0.05, 1.0))
+    p[:, 3] = np.maximum(p[:, 3], 0.02)  # keep the oracle reference quick
+    q = W.q_grid(16)[[0, 17, 100, 255]]
+    cfg = dict(params=p, q=q, ff=W.ff_box(1), L=1, channels=3)
+    out, e, st, rc = ctx.integrate(p, q, cfg["ff"], 1, rtol=1e-6, err=True)
+    assert rc == P.OK
+    picks = W.containers(cfg)
+    ref = oracle_refs(cfg, picks, 1e-9)
+    for k, (ip, iq, ch) in enumerate(picks):
+        assert gate_ratio(out[ip, iq, ch], ref[k], 1e-6) <= 1.0, (ip, iq, ch)
+        assert (e[ip, iq, ch] >= 0).all()
+
+
+@pytest.mark.parametrize("ch", [1, 2, 3])
+def test_channel_subsets_and_edge_momenta(ctx, P, ch):
+    p = np.array([[1.0, -0.25, -0.95, 0.05, 0.2]])
+    q = np.array([[math.pi, math.pi], [-math.pi, 0.0], [0.0, 0.0], [7.5, -13.0], [1.0, 2.0]])
+    out, _, st, rc = ctx.integrate(p, q, W.ff_box(1), 1, channels=ch, rtol=1e-7)
+    assert rc == P.OK and out.shape == (1, 5, 1 if ch < 3 else 2, 9, 9)
+    chans = [c for c, bit in ((O.PP, 1), (O.PH, 2)) if ch & bit]
+    cfg = dict(params=p, q=q, ff=W.ff_box(1), L=1, channels=ch)
+    ref = oracle_refs(cfg, W.containers(cfg), 1e-10)
+    for k, (ip, iq, c) in enumerate(W.containers(cfg)):
+        assert gate_ratio(out[ip, iq, chans.index(c)], ref[k], 1e-7) <= 1.0
+
+
+@pytest.mark.parametrize("ff_name", ["ff5", "ff25", "ff1"])
+def test_form_factor_sets(ctx, P, ff_name):
+    ff, L = {"ff5": (W.ff5(), 1), "ff25": (W.ff_box(2), 2), "ff1": (W.ff_box(0), 0)}[ff_name]
+    p = np.array([[1.0, -0.3, -1.1, 0.05, 0.3]])
+    q = np.array([[2.88, 0.26], [0.0, 0.0]])
+    out, _, st, rc = ctx.integrate(p, q, ff, L, rtol=1e-6)
+    assert rc == P.OK
+    cfg = dict(params=p, q=q, ff=ff, L=L, channels=3)
+    ref = oracle_refs(cfg, W.containers(cfg), 1e-9)
+    for k, (ip, iq, c) in enumerate(W.containers(cfg)):
+        assert gate_ratio(out[ip, iq, c], ref[k], 1e-6) <= 1.0
+
+
+def test_unit_and_gaussian_integrands(P):
+    with P.Context(kind=P.UNIT, max_regions=1 << 16) as c:
+        out, _, _, rc = c.integrate([[1, 0, 0, 0.1, 0.1]], [[0.3, 0.2]], W.ff_box(2), 2,
+                                    rtol=1e-10, atol=1e-12)
+        assert rc == P.OK
+        assert np.abs(out[0, 0, 0] - np.eye(25)).max() < 1e-10
+    x0, y0, s = 0.7, -2.9, 0.15
+    with P.Context(kind=P.GAUSS, gauss=(x0, y0, s), max_regions=1 << 14) as c:
+        out, e, _, rc = c.integrate([[1, 0, 0, 0.1, 0.1]], [[0.0, 0.0]], W.ff_box(0), 0,
+                                    channels=P.PH, rtol=1e-10, err=True)
+        from scipy import special
+        f = lambda cc: special.ndtr((math.pi - cc) / s) - special.ndtr((-math.pi - cc) / s)
+        exact = 2 * math.pi * s * s * f(x0) * f(y0) / (4 * math.pi ** 2)
+        assert abs(out[0, 0, 0, 0, 0] - exact) <= 1e-10 * exact
+        assert abs(out[0, 0, 0, 0, 0] - exact) <= e[0, 0, 0, 0, 0] + 1e-16
+
+
+def test_per_integral_mode(P):
+    p = np.array([[1.0, -0.25, -0.95, 0.05, 0.2]])
+    q = np.array([[1.57, 1.31]])
+    with P.Context(err_mode=P.ERR_PER_INTEGRAL, max_regions=1 << 17) as c:
+        out, e, st, rc = c.integrate(p, q, W.ff_box(1), 1, rtol=1e-6, err=True)
+    assert rc == P.OK
+    tau = 1e-6 * np.maximum(np.abs(out), NU * np.abs(out).max(axis=(-1, -2), keepdims=True))
+    assert (e <= tau * (1 + 1e-9)).all()
+    cfg = dict(params=p, q=q, ff=W.ff_box(1), L=1, channels=3)
+    ref = oracle_refs(cfg, W.containers(cfg), 1e-10)
+    for k, (ip, iq, c) in enumerate(W.containers(cfg)):
+        assert gate_ratio(out[ip, iq, c], ref[k], 1e-6) <= 1.0
+
+
+def test_budget_exhaustion_reports_noconv(P):
+    with P.Context(max_regions=64) as c:
+        out, e, st, rc = c.integrate([[1.0, -0.25, -0.95, 0.01, 0.01]], [[1.0, 0.5]],
+                                     W.ff_box(1), 1, rtol=1e-9, err=True)
+    assert rc == P.ENOCONV and st["not_converged"] == 2
+    assert np.isfinite(out).all() and (e > 0).any()
+
+
+def test_results_are_bitwise_reproducible(ctx, P):
+    cfg = W.config("C1")
+    a, _, _, _ = ctx.integrate(cfg["params"], cfg["q"][:20], cfg["ff"], 1, rtol=1e-6)
+    b, _, _, _ = ctx.integrate(cfg["params"], cfg["q"][:20], cfg["ff"], 1, rtol=1e-6)
+    assert np.array_equal(a, b)
+
+
+def test_invalid_arguments_are_rejected(ctx, P):
+    p = [[1.0, 0.0, 0.0, 0.1, 0.1]]
+    bad = [dict(ff=np.ones((2, 9)), L=1), dict(ff=W.ff_box(1), L=3),
+           dict(ff=W.ff_box(1), L=1, channels=0), dict(ff=W.ff_box(1), L=1, rtol=0.0),
+           dict(ff=W.ff_box(1), L=1, params=[[1.0, 0.0, 0.0, 0.0, 0.1]])]
+    for b in bad:
+        with pytest.raises(P.PaidError) as ei:
+            ctx.integrate(b.get("params", p), [[0.1, 0.2]], b["ff"], b["L"],
+                          channels=b.get("channels", 3), rtol=b.get("rtol", 1e-6))
+        assert ei.value.code == P.EINVAL
+
+
+def test_full_size_workload_sampled(P):
+    """The benchmark's workload at full size (23,040 containers, one call, the
+    benchmark's launch configuration), sampled containers against the oracle."""
+    cfg = W.config("C2")
+    c = P.Context()
+    out, _, st, rc = c.integrate(cfg["params"], cfg["q"], cfg["ff"], cfg["L"], rtol=1e-6)
+    c.close()
+    assert rc == P.OK and st["not_converged"] == 0 and np.isfinite(out).all()
+    rng = np.random.default_rng(5)
+    picks = [(ip, int(rng.integers(0, 576)), int(rng.integers(0, 2))) for ip in (0, 5, 9, 12, 14)]
+    ref = oracle_refs(cfg, picks, 1e-9)
+    for k, (ip, iq, ch) in enumerate(picks):
+        assert gate_ratio(out[ip, iq, ch], ref[k], 1e-6) <= 1.0, (ip, iq, ch)
+    # symmetry of every output matrix
+    assert np.array_equal(out, np.swapaxes(out, -1, -2))
