@@ -25,19 +25,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "integrals/s at rtol 1e-6, plain vs batched+learned-seeded, 1 MI355X"
-PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (vector and matrix)
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64: vector (256 CUs x 4 SIMD x 16 lanes x 2 x 2.4 GHz) and matrix
 
 # Algorithmic work of one region-evaluation work item (a parent and its four
-# children, rule pair N = 4 / 2N = 8, shared 17 x 17 node grid):
-#   integrand: 289 nodes x 118 FP64 flops (dispersion 12, switch 8, map 4,
-#              three Horner chains of degree 15 = 90, combine 4);
-#   projection: 4 children x 2 M^2 (n_2N + n_N) = 4 x 2 M^2 (81 + 25).
+# children, rule pair N = 4 / 2N = 8, shared 17 x 17 node grid), in FP64 flops
+# (an FMA counts 2):
+#   integrand: 289 nodes x 118 (dispersion 12, close-pair switch 8, interval
+#              map 4, three Horner chains of degree 15 = 90, combine 4);
+#   separable projection with NP = NB(NB+1)/2 axis products, NB = 2L+1:
+#     y-sums  2 x 17 x NP x 27 (fine: 9 mul + 9 FMA) + 2 x 9 x NP x 10 (coarse: 5 FMA)
+#     x-sums  4 children x NP^2 x 42 (fine 9 x (mul + FMA), coarse 5 x (mul + FMA))
+#     pairs   4 children x MB(MB+1)/2 x 3
+#   dense projection (matrix cores): 4 children x 2 M^2 (81 + 25).
 K_FLOPS_PER_NODE = 118
 NODES_PER_ITEM = 289
 
 
-def item_flops(M: int) -> int:
-    return NODES_PER_ITEM * K_FLOPS_PER_NODE + 4 * 2 * M * M * (81 + 25)
+def item_flops(M: int, L: int, separable: bool) -> int:
+    k = NODES_PER_ITEM * K_FLOPS_PER_NODE
+    if not separable:
+        return k + 4 * 2 * M * M * (81 + 25)
+    nb = 2 * L + 1
+    np_ = nb * (nb + 1) // 2
+    mb = nb * nb
+    return (k + 2 * 17 * np_ * 27 + 2 * 9 * np_ * 10 + 4 * np_ * np_ * 42
+            + 4 * mb * (mb + 1) // 2 * 3)
 
 
 def cpu_baseline(cfg, budget_s: float, threads: int, seed: int = 11):
@@ -77,6 +89,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--variants", action="store_true", help="also time one call per flow scale")
+    ap.add_argument("--gram", choices=["separable", "mfma"], default="separable")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (the reference "
+                         "for scaling the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -85,6 +101,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes": n * 8}))
+        return
     import paid_1610_09991_amd as P
     import workloads as W
 
@@ -97,7 +122,8 @@ def main():
     n_int = n_ctr * MU
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    ctx = P.Context(stream=stream.cuda_stream, profile=1)
+    ctx = P.Context(stream=stream.cuda_stream, profile=1,
+                    gram=P.GRAM_SEPARABLE if args.gram == "separable" else P.GRAM_MFMA)
     out = torch.empty((len(params), len(q), nch, M, M), dtype=torch.float64, device=dev)
     run = lambda o: ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=o)
 
@@ -121,13 +147,16 @@ def main():
     items = sum(s["eval_items"] for s in stats)
     ev_s = sum(s["eval_seconds"] for s in stats)
     launches = sum(s["eval_launches"] for s in stats)
-    flops_launch = item_flops(M) * items / max(launches, 1)
+    sep = ctx.cfg.gram == P.GRAM_SEPARABLE
+    fpi = item_flops(M, L, sep)
+    flops_launch = fpi * items / max(launches, 1)
     avg_launch = ev_s / max(launches, 1)
     achieved = flops_launch / avg_launch / 1e12 if avg_launch > 0 else 0.0
-    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-            "kernel": "k_children (region evaluation)", "launches": launches,
-            "avg_launch_ms": 1e3 * avg_launch, "flops_per_item": item_flops(M),
+    roof = {"bound": "alu" if sep else "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "kernel": "k_children (region evaluation, %s projection)" %
+                      ("separable FP64" if sep else "FP64 matrix-core"),
+            "launches": launches, "avg_launch_ms": 1e3 * avg_launch, "flops_per_item": fpi,
             "items": items, "eval_share_of_step": ev_s / dt}
 
     line = {"metric": METRIC, "value": value, "unit": "integrals/s", "n_gpus": 1,

@@ -79,8 +79,8 @@ enum {
 
 /* how the projection F^T diag(w g) F is formed */
 enum {
-  PAID_GRAM_MFMA = 0,      /* dense weighted Gram contraction on the matrix cores */
-  PAID_GRAM_SEPARABLE = 1  /* the same sums factored along the two axes (FP64 only) */
+  PAID_GRAM_MFMA = 0,      /* dense weighted Gram contraction on the FP64 matrix cores */
+  PAID_GRAM_SEPARABLE = 1  /* the same sums factored along the two axes (default) */
 };
 
 typedef struct {
@@ -125,7 +125,8 @@ typedef struct {
 } paid_stats;
 
 /* Fill *cfg with defaults (device 0, N = 4, batch 8, batch_max 1024, global
- * error, FP64, MFMA Gram, nu = 1e-3, max_regions = 2^18, automatic pool). */
+ * error, FP64, separable projection, nu = 1e-3, max_regions = 2^18,
+ * automatic pool). */
 int paid_config_default(paid_config *cfg);
 
 /* Create a context on cfg->device.  *out receives the context (NULL on

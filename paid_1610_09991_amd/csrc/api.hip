@@ -254,7 +254,7 @@ int paid_config_default(paid_config *cfg) {
   cfg->batch_max = 1024;
   cfg->err_mode = PAID_ERR_GLOBAL;
   cfg->precision = PAID_FP64;
-  cfg->gram = PAID_GRAM_MFMA;
+  cfg->gram = PAID_GRAM_SEPARABLE;
   cfg->kind = PAID_BUBBLE_DOT;
   cfg->nu = 1e-3;
   cfg->max_regions = 1L << 18;
@@ -276,7 +276,8 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
   if (cfg.err_mode != PAID_ERR_GLOBAL && cfg.err_mode != PAID_ERR_PER_INTEGRAL)
     return fail(nullptr, PAID_EINVAL, "bad err_mode");
   if (cfg.precision != PAID_FP64) return fail(nullptr, PAID_EINVAL, "precision mode not built");
-  if (cfg.gram != PAID_GRAM_MFMA) return fail(nullptr, PAID_EINVAL, "gram mode not built");
+  if (cfg.gram != PAID_GRAM_MFMA && cfg.gram != PAID_GRAM_SEPARABLE)
+    return fail(nullptr, PAID_EINVAL, "bad gram mode");
   if (cfg.kind < 0 || cfg.kind > 3) return fail(nullptr, PAID_EINVAL, "bad kind");
   if (cfg.kind == PAID_GAUSS && !(cfg.gauss[2] > 0)) return fail(nullptr, PAID_EINVAL, "gauss width must be > 0");
   if (cfg.max_regions < 16 || cfg.max_regions > (1L << 28))
@@ -649,6 +650,7 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
   P.n_ctr = 1;
   P.kind = cfg.kind;
   P.err_mode = PAID_ERR_GLOBAL;
+  P.gram = cfg.gram;
   P.gauss_x = cfg.gauss[0];
   P.gauss_y = cfg.gauss[1];
   P.gauss_s = cfg.gauss[2];

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "paid.h"
 #include "paid_device.h"
 
 namespace paid {
@@ -53,6 +54,7 @@ struct Problem {      // everything the round kernels need, passed by value
   int W;                      // slots
   long cap;                   // regions per slot
   int bmin, bmax;
+  int lds_wave_doubles;       // per-wave LDS of the evaluation kernel (set at launch)
   uint64_t *code;             // [W*cap]
   double *key;                // [W*cap]
   double *Q;                  // [W*cap*MU]

@@ -69,38 +69,72 @@ __device__ inline int block_scan(int v, int *sh, int &excl) {
   return tot;
 }
 
-// Sum over the leaves of a slot, in a fixed order, of Q (into val) and of
-// the per-pair errors (into errp, when stored); returns the sum of the keys.
-__device__ double resum_leaves(const Problem &P, int s, double *shd) {
-  const int t = threadIdx.x, lane = t & 63, grp = t >> 6, ng = blockDim.x >> 6;
-  const long n = P.nleaf[s], base = (long)s * P.cap;
-  for (int c0 = 0; c0 < P.MU; c0 += 64) {
-    int pid = c0 + lane;
-    double aq = 0.0, ae = 0.0;
-    if (pid < P.MU) {
-      for (long i = grp; i < n; i += ng) {
-        aq += P.Q[(base + i) * P.MU + pid];
-        if (P.E) ae += (double)P.E[(base + i) * P.MU + pid];
+// Column sums of a row-major block A[rows][ncol] (float or double), in a
+// fixed order: with ncol <= blockDim, thread t owns column t % ncol and the
+// rows congruent to t / ncol modulo R = blockDim / ncol, reads are coalesced
+// and four independent accumulators keep loads in flight; the R partials of
+// a column are then added in order.  Wider blocks go column by column.
+template <class T>
+__device__ void column_sums(const T *A, long rows, int ncol, double *out, double *shd) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (ncol <= nt) {
+    const int R = nt / ncol, span = R * ncol;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (t < span) {
+      const long N = rows * ncol;
+      long e = t;
+      for (; e + 3 * (long)span < N; e += 4 * (long)span) {
+        a0 += (double)A[e];
+        a1 += (double)A[e + span];
+        a2 += (double)A[e + 2 * (long)span];
+        a3 += (double)A[e + 3 * (long)span];
       }
+      for (; e < N; e += span) a0 += (double)A[e];
     }
-    shd[t] = aq;
-    shd[blockDim.x + t] = ae;
+    shd[t] = (a0 + a1) + (a2 + a3);
     __syncthreads();
-    if (grp == 0 && pid < P.MU) {
-      double sq = 0.0, se = 0.0;
-      for (int g = 0; g < ng; ++g) {
-        sq += shd[g * 64 + lane];
-        se += shd[blockDim.x + g * 64 + lane];
+    if (t < ncol) {
+      double s = 0.0;
+      for (int r = 0; r < R; ++r) s += shd[r * ncol + t];
+      out[t] = s;
+    }
+    __syncthreads();
+  } else {
+    for (int c = t; c < ncol; c += nt) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      long i = 0;
+      for (; i + 3 < rows; i += 4) {
+        a0 += (double)A[i * ncol + c];
+        a1 += (double)A[(i + 1) * ncol + c];
+        a2 += (double)A[(i + 2) * ncol + c];
+        a3 += (double)A[(i + 3) * ncol + c];
       }
-      P.val[(long)s * P.MU + pid] = sq;
-      if (P.errp) P.errp[(long)s * P.MU + pid] = se;
+      for (; i < rows; ++i) a0 += (double)A[i * ncol + c];
+      out[c] = (a0 + a1) + (a2 + a3);
     }
     __syncthreads();
   }
-  double ks = 0.0;
-  for (long i = t; i < n; i += blockDim.x) ks += P.key[base + i];
-  double k = block_sum(ks, shd);
+}
+
+// Sum of the leaf keys of a slot (fixed order); with per-pair errors stored,
+// also their column sums.  The values themselves are the running FP64 sums
+// of Q over the leaves (updated at every split).
+__device__ double resum_errors(const Problem &P, int s, double *shd) {
+  const int t = threadIdx.x;
+  const long n = P.nleaf[s], base = (long)s * P.cap;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  long i = t;
+  const long st = blockDim.x;
+  for (; i + 3 * st < n; i += 4 * st) {
+    a0 += P.key[base + i];
+    a1 += P.key[base + i + st];
+    a2 += P.key[base + i + 2 * st];
+    a3 += P.key[base + i + 3 * st];
+  }
+  for (; i < n; i += st) a0 += P.key[base + i];
+  double k = block_sum((a0 + a1) + (a2 + a3), shd);
   if (t == 0) P.err[s] = k;
+  if (P.E) column_sums(P.E + base * P.MU, n, P.MU, P.errp + (long)s * P.MU, shd);
   __syncthreads();
   return k;
 }
@@ -162,8 +196,8 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
   }
   double eps, deficit;
   int conv = tolerance_test(P, s, shd, eps, deficit);
-  if (conv) {  // accept only on sums recomputed from the leaves
-    resum_leaves(P, s, shd);
+  if (conv) {  // accept only on error sums recomputed from the leaves
+    resum_errors(P, s, shd);
     conv = tolerance_test(P, s, shd, eps, deficit);
     if (conv) {
       if (t == 0) {
@@ -343,33 +377,17 @@ __global__ void k_admit(Problem P) {
 
 __global__ void __launch_bounds__(kSelThreads) k_update(Problem P) {
   __shared__ double shd[2 * kSelThreads];
+  __shared__ double colv[kMaxMU], colp[kMaxMU];
   const int s = blockIdx.x, t = threadIdx.x;
   if (s >= P.W) return;
   const int k = P.selcnt[s];
   if (k == 0) return;
-  const int lane = t & 63, grp = t >> 6, ng = blockDim.x >> 6;
   const long it0 = (long)s * P.bmax;
-  for (int c0 = 0; c0 < P.MU; c0 += 64) {
-    int pid = c0 + lane;
-    double av = 0.0, ap = 0.0;
-    if (pid < P.MU)
-      for (int r = grp; r < k; r += ng) {
-        av += P.dv[(it0 + r) * P.MU + pid];
-        if (P.dep) ap += P.dep[(it0 + r) * P.MU + pid];
-      }
-    shd[t] = av;
-    shd[blockDim.x + t] = ap;
-    __syncthreads();
-    if (grp == 0 && pid < P.MU) {
-      double sv = 0.0, sp = 0.0;
-      for (int g = 0; g < ng; ++g) {
-        sv += shd[g * 64 + lane];
-        sp += shd[blockDim.x + g * 64 + lane];
-      }
-      P.val[(long)s * P.MU + pid] += sv;
-      if (P.errp) P.errp[(long)s * P.MU + pid] += sp;
-    }
-    __syncthreads();
+  column_sums(P.dv + it0 * P.MU, k, P.MU, colv, shd);
+  if (P.dep) column_sums(P.dep + it0 * P.MU, k, P.MU, colp, shd);
+  for (int pid = t; pid < P.MU; pid += blockDim.x) {
+    P.val[(long)s * P.MU + pid] += colv[pid];
+    if (P.errp) P.errp[(long)s * P.MU + pid] += colp[pid];
   }
   double de = 0.0;
   for (int r = t; r < k; r += blockDim.x) de += P.de[it0 + r];
@@ -386,7 +404,7 @@ __global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
   __shared__ double shd[2 * kSelThreads];
   const int s = blockIdx.x, t = threadIdx.x;
   if (s >= P.W || P.state[s] != SLOT_DONE) return;
-  if (P.flags[s] & 2) resum_leaves(P, s, shd);  // budget exit: sums from the leaves
+  if (P.flags[s] & 2) resum_errors(P, s, shd);  // budget exit: error sums from the leaves
   const long c = P.cid[s];
   const int M = P.M;
   for (int pid = t; pid < P.MU; pid += blockDim.x) {

@@ -4,13 +4,20 @@
 // One wavefront owns one work item: a parent rectangle and its four children
 // (Alg. 2: split into 4, evaluate Q_N and Q_2N on each).  The children share
 // 17 x 17 node coordinates, so the integrand g is evaluated 289 times instead
-// of 324.  Per child the projection onto the form factors is the weighted
-// Gram contraction
-//     Q_2N = U^T diag(w_2N g) U,   E = U^T diag((w_2N - w_N) g) U = Q_2N - Q_N,
-// with U[node][m] the box basis at the 81 nodes, on the FP64 matrix cores
-// (16x16x4 tiles; a 9-function basis fills one tile, 25 functions 2x2 tiles of
-// which the lower-left one is skipped by symmetry).  err of a child is
-// sum_pq |E_pq| (the paper's global error summed over pairs).
+// of 324.  Per child the projection onto the box basis U[node][m] is the
+// weighted Gram contraction
+//     Q_2N = U^T diag(w_2N g) U,    Q_N = U^T diag(w_N g) U,   E = Q_2N - Q_N,
+// and err of a child is sum_pq |E_pq| (the paper's error summed over pairs).
+// Two ways to form it:
+//   - separable (default): U[node][(a,b)] = u_a(x) u_b(y) and the weights are
+//     tensor products, so the sum runs first over y for every x and every
+//     product u_b u_d, then over x for every product u_a u_c; for 9 form
+//     factors this is ~4.4k FMAs per parent instead of a 16x16x84 tile pair;
+//   - dense Gram on the FP64 matrix cores (16x16x4 tiles; a 9-function basis
+//     fills one tile, 25 functions 2x2 tiles of which the lower-left one is
+//     skipped by symmetry).
+// The frequency-sum table of the parameter row is staged in LDS once per
+// workgroup and shared by its waves.
 #include <math.h>
 
 #include "launch.h"
@@ -28,24 +35,57 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
 constexpr double kSqrt2 = 1.41421356237309504880;
+constexpr int kTabRowsLds = 48;  // table rows a workgroup holds in LDS
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// per-wave scratch in LDS
-struct WaveLds {
-  double g[kNX * kNX];             // integrand at the shared nodes
-  double cp[2][kNX], cm[2][kNX];   // cos(l/2 + p), cos(l/2 - p) per axis
-  double u[2][kNX][kMaxNB];        // box harmonics per axis
-  double pos[2][kNX];              // coordinates
-  double cq[kMaxMU], ce[kMaxMU];   // one child's Q_2N and E over form-factor pairs
-  double tq[kMaxMB * kMaxMB];      // box Gram of Q_2N (general form-factor sets only)
-  double ts[kMaxMB * kMaxMB];      // box Gram of E
-  double tr[kMaxMB * kMaxMB];      // half-transformed Gram
+template <int L>
+struct Dims {
+  static constexpr int NB = 2 * L + 1;          // harmonics per axis
+  static constexpr int MB = NB * NB;            // box functions
+  static constexpr int NP = NB * (NB + 1) / 2;  // products u_a u_c, a <= c
+  static constexpr int MU = MB * (MB + 1) / 2;  // pairs of box functions
 };
 
-__device__ inline void wave_sync() { __syncthreads(); }  // one wave per workgroup
+// per-wave scratch in LDS
+template <int L>
+struct WaveLds {
+  static constexpr int NB = Dims<L>::NB, MB = Dims<L>::MB, NP = Dims<L>::NP, MU = Dims<L>::MU;
+  double g[kNX * kNX];             // integrand at the shared nodes
+  double cp[2][kNX], cm[2][kNX];   // cos(l/2 + p), cos(l/2 - p) per axis
+  double u[2][kNX][NB];            // box harmonics per axis
+  double pp[2][kNX][NP];           // their products u_a u_c per axis
+  double pos[2][kNX];              // coordinates
+  double h2[2][kNX][NP];           // y-sums with the fine weights, per child row
+  double h1[2][kNCo * 2 - 1][NP];  // y-sums with the coarse weights (even x)
+  double g2[NP * NP], g1[NP * NP]; // x-sums of one child
+  double cq[MU], ce[MU];           // one child's Q_2N and E over form-factor pairs
+  // general form-factor sets only (dropped from the allocation otherwise)
+  double tq[MB * MB], ts[MB * MB], tr[MB * MB];
+};
+
+template <int L>
+constexpr size_t wave_lds_doubles(bool identity) {
+  return (sizeof(WaveLds<L>) - (identity ? 3 * sizeof(double) * Dims<L>::MB * Dims<L>::MB : 0)) /
+         sizeof(double);
+}
+
+// wave-local synchronisation for LDS traffic between lanes of one wave
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int lane_id() { return threadIdx.x & 63; }
 
 __device__ inline int pair_index(int p, int q, int M) { return p * M - p * (p - 1) / 2 + (q - p); }
+
+template <int NB>
+__device__ inline int prod_index(int a, int c) {  // (a, c) -> index of u_a u_c
+  if (a > c) { int t = a; a = c; c = t; }
+  return a * NB - a * (a - 1) / 2 + (c - a);
+}
 
 // Coordinates of one axis: nco = 17 (four children of a rectangle of width
 // wdt starting at x0) or 9 (a single rectangle).
@@ -55,10 +95,13 @@ __device__ inline double axis_coord(int j, int nco, double x0, double wdt) {
   return x0 + 0.75 * wdt + 0.25 * wdt * c_rule.xi[j - 8];
 }
 
-// Fill per-axis data and the integrand on the nco x nco node grid.
-__device__ void fill_nodes(WaveLds &S, const Problem &P, const Ctr &C, const Entry &E,
+// Per-axis data and the integrand on the nco x nco node grid.  `tab` is the
+// parameter row's frequency-sum table (LDS or global memory).
+template <int L>
+__device__ void fill_nodes(WaveLds<L> &S, const Problem &P, const Ctr &C, const Entry &E,
                            const double *tab, int nco, double x0, double y0, double wdt) {
-  const int lane = threadIdx.x;
+  constexpr int NB = Dims<L>::NB;
+  const int lane = lane_id();
   if (lane < 2 * nco) {
     int ax = lane >= nco, j = lane - ax * nco;
     double p = axis_coord(j, nco, ax ? y0 : x0, wdt);
@@ -68,14 +111,21 @@ __device__ void fill_nodes(WaveLds &S, const Problem &P, const Ctr &C, const Ent
     S.pos[ax][j] = p;
     S.cp[ax][j] = cL * cpp - sL * sp;  // cos(l/2 + p)
     S.cm[ax][j] = cL * cpp + sL * sp;  // cos(l/2 - p)
-    S.u[ax][j][0] = 1.0;
-    if (P.L >= 1) {
-      S.u[ax][j][1] = kSqrt2 * cpp;
-      S.u[ax][j][2] = kSqrt2 * sp;
+    double u[NB];
+    u[0] = 1.0;
+    if (L >= 1) {
+      u[1] = kSqrt2 * cpp;
+      u[2] = kSqrt2 * sp;
     }
-    if (P.L >= 2) {
-      S.u[ax][j][3] = kSqrt2 * (cpp - sp) * (cpp + sp);
-      S.u[ax][j][4] = kSqrt2 * 2.0 * sp * cpp;
+    if (L >= 2) {
+      u[3] = kSqrt2 * (cpp - sp) * (cpp + sp);
+      u[4] = kSqrt2 * 2.0 * sp * cpp;
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      S.u[ax][j][a] = u[a];
+#pragma unroll
+      for (int c = a; c < NB; ++c) S.pp[ax][j][prod_index<NB>(a, c)] = u[a] * u[c];
     }
   }
   wave_sync();
@@ -100,16 +150,79 @@ __device__ void fill_nodes(WaveLds &S, const Problem &P, const Ctr &C, const Ent
   wave_sync();
 }
 
+// ------------------------------------------------------------- separable
+// Stage 1: for every x of the grid and each child row cy, the y-sums
+//   h2[cy][x][k] = sum_b w2_b g(x, y_b) P_k(y_b),  h1 likewise with w1 on even b.
+template <int L>
+__device__ void sep_stage1(WaveLds<L> &S, int nco, int nrow) {
+  constexpr int NP = Dims<L>::NP;
+  const int lane = lane_id();
+  for (int idx = lane; idx < nrow * nco * NP; idx += 64) {
+    int cy = idx / (nco * NP), rem = idx - cy * nco * NP, x = rem / NP, k = rem - x * NP;
+    const double *gr = &S.g[x * nco + 8 * cy];
+    double s2 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int b = 0; b < kNF; ++b) {
+      double v = gr[b] * S.pp[1][8 * cy + b][k];
+      s2 = fma(c_rule.w2[b], v, s2);
+      if (!(b & 1)) s1 = fma(c_rule.w1[b >> 1], v, s1);
+    }
+    S.h2[cy][x][k] = s2;
+    if (!(x & 1)) S.h1[cy][x >> 1][k] = s1;
+  }
+  wave_sync();
+}
+
+// Stage 2 for child (cx, cy), then the form-factor pairs (identity basis) or
+// the full box Gram (general sets) scaled by the area factor fa.
+template <int L>
+__device__ void sep_stage2(WaveLds<L> &S, const Problem &P, const int *pidmap, int cx, int cy,
+                           double fa) {
+  constexpr int NB = Dims<L>::NB, NP = Dims<L>::NP, MB = Dims<L>::MB, MU = Dims<L>::MU;
+  const int lane = lane_id();
+  for (int idx = lane; idx < NP * NP; idx += 64) {
+    int j = idx / NP, k = idx - j * NP;
+    double s2 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int a = 0; a < kNF; ++a) {
+      int x = 8 * cx + a;
+      double pj = S.pp[0][x][j];
+      s2 = fma(c_rule.w2[a] * pj, S.h2[cy][x][k], s2);
+      if (!(a & 1)) s1 = fma(c_rule.w1[a >> 1] * pj, S.h1[cy][x >> 1][k], s1);
+    }
+    S.g2[idx] = s2;
+    S.g1[idx] = s1;
+  }
+  wave_sync();
+  if (P.ff_identity) {
+    for (int pid = lane; pid < MU; pid += 64) {
+      int jk = pidmap[pid];
+      double q2 = S.g2[jk];
+      S.cq[pid] = fa * q2;
+      S.ce[pid] = fa * (q2 - S.g1[jk]);
+    }
+  } else {
+    for (int idx = lane; idx < MB * MB; idx += 64) {
+      int m = idx / MB, n = idx - m * MB;
+      int jk = prod_index<NB>(m / NB, n / NB) * NP + prod_index<NB>(m % NB, n % NB);
+      double q2 = S.g2[jk];
+      S.tq[idx] = fa * q2;
+      S.ts[idx] = fa * (q2 - S.g1[jk]);
+    }
+  }
+  wave_sync();
+}
+
+// ------------------------------------------------------------- dense MFMA
 // Weighted Gram of one rectangle on the FP64 matrix cores.  Its 9 x 9 nodes
-// are rows offx.. and columns offy.. of the nco x nco grid.  Results go to
-// S.cq / S.ce (identity form factors) or S.tq / S.ts (box Gram, general).
-template <int NT>
-__device__ void gram_fp64(WaveLds &S, const Problem &P, int nco, int offx, int offy, double fa) {
-  const int lane = threadIdx.x, m = lane & 15, kk = lane >> 4;
-  const int MB = P.MB, nb = P.nb;
+// are rows offx.. and columns offy.. of the nco x nco grid.
+template <int L>
+__device__ void gram_mfma(WaveLds<L> &S, const Problem &P, int nco, int offx, int offy, double fa) {
+  constexpr int NB = Dims<L>::NB, MB = Dims<L>::MB, NT = MB > 16 ? 2 : 1;
+  const int lane = lane_id(), m = lane & 15, kk = lane >> 4;
   const bool v0 = m < MB, v1 = (NT == 2) && (m + 16 < MB);
-  const int a0 = v0 ? m / nb : 0, b0 = v0 ? m - (m / nb) * nb : 0;
-  const int a1 = v1 ? (m + 16) / nb : 0, b1 = v1 ? (m + 16) - ((m + 16) / nb) * nb : 0;
+  const int a0 = v0 ? m / NB : 0, b0 = v0 ? m % NB : 0;
+  const int a1 = v1 ? (m + 16) / NB : 0, b1 = v1 ? (m + 16) % NB : 0;
   constexpr int NACC = NT * (NT + 1) / 2;
   d4 aq[NACC], ae[NACC];
 #pragma unroll
@@ -167,13 +280,14 @@ __device__ void gram_fp64(WaveLds &S, const Problem &P, int nco, int offx, int o
 }
 
 // General form-factor sets: Q_ff = C Q_box C^T for both Q and E.
-__device__ void transform_ff(WaveLds &S, const Problem &P) {
-  const int lane = threadIdx.x, MB = P.MB, M = P.M;
+template <int L>
+__device__ void transform_ff(WaveLds<L> &S, const Problem &P) {
+  constexpr int MB = Dims<L>::MB;
+  const int lane = lane_id(), M = P.M;
   double *R = S.tr;
   for (int which = 0; which < 2; ++which) {
     const double *G = which ? S.ts : S.tq;
-    // R[a][q] = sum_b G[a][b] C[q][b]
-    for (int idx = lane; idx < MB * M; idx += 64) {
+    for (int idx = lane; idx < MB * M; idx += 64) {  // R[a][q] = sum_b G[a][b] C[q][b]
       int a = idx / M, q = idx - a * M;
       double s = 0.0;
       for (int b = 0; b < MB; ++b) s = fma(G[a * MB + b], P.ffc[q * MB + b], s);
@@ -194,15 +308,15 @@ __device__ void transform_ff(WaveLds &S, const Problem &P) {
 }
 
 __device__ inline double wave_sum(double v) {
-  // fixed butterfly order: deterministic
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);  // fixed order
   return v;
 }
 
 // Store one evaluated rectangle (S.cq, S.ce) into pool slot `ri` of slot s,
 // return its key.
-__device__ double store_region(WaveLds &S, const Problem &P, int s, long ri, uint64_t code) {
-  const int lane = threadIdx.x;
+template <int L>
+__device__ double store_region(WaveLds<L> &S, const Problem &P, int s, long ri, uint64_t code) {
+  const int lane = lane_id();
   const long base = (long)s * P.cap + ri;
   double part = 0.0;
   for (int pid = lane; pid < P.MU; pid += 64) {
@@ -219,29 +333,51 @@ __device__ double store_region(WaveLds &S, const Problem &P, int s, long ri, uin
   return key;
 }
 
-template <int NT>
-__device__ void eval_rect(WaveLds &S, const Problem &P, int nco, int offx, int offy, double fa) {
-  gram_fp64<NT>(S, P, nco, offx, offy, fa);
-  if (!P.ff_identity) transform_ff(S, P);
+// One rectangle of the grid (child (cx, cy) of the 17-grid, or the 9-grid
+// root with cx = cy = 0): fills S.cq / S.ce.
+template <int L, int GRAM>
+__device__ void eval_rect(WaveLds<L> &S, const Problem &P, const int *pidmap, int nco, int cx,
+                          int cy, double fa) {
+  if (GRAM == PAID_GRAM_SEPARABLE) {
+    sep_stage2<L>(S, P, pidmap, cx, cy, fa);
+  } else {
+    gram_mfma<L>(S, P, nco, 8 * cx, 8 * cy, fa);
+  }
+  if (!P.ff_identity) transform_ff<L>(S, P);
+}
+
+// pair index -> index into the x-sum matrix of the separable form
+template <int L>
+__device__ void build_pidmap(int *map, int tid, int nthr) {
+  constexpr int NB = Dims<L>::NB, MB = Dims<L>::MB, NP = Dims<L>::NP, MU = Dims<L>::MU;
+  for (int pid = tid; pid < MU; pid += nthr) {
+    int m = 0, k = pid;
+    while (k >= MB - m) { k -= MB - m; ++m; }
+    int n = m + k;
+    map[pid] = prod_index<NB>(m / NB, n / NB) * NP + prod_index<NB>(m % NB, n % NB);
+  }
 }
 
 // ---------------------------------------------------------------- root
-template <int NT>
+template <int L, int GRAM>
 __global__ void __launch_bounds__(64) k_root(Problem P) {
   extern __shared__ double lds_raw[];
-  WaveLds &S = *reinterpret_cast<WaveLds *>(lds_raw);
+  __shared__ int pidmap[Dims<L>::MU];
+  WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw);
   const int s = blockIdx.x;
   if (s >= P.W || P.state[s] != SLOT_NEW) return;
+  build_pidmap<L>(pidmap, threadIdx.x, 64);
   const int c = P.cid[s];
   const Ctr C = P.ctr[c];
   const Entry E = P.entries[C.entry];
   const double *tab = P.tab + E.tab_off;
   // key weights for the per-integral mode start at one
   for (int pid = threadIdx.x; pid < P.MU; pid += 64) P.itau[(long)s * P.MU + pid] = 1.0f;
-  wave_sync();
-  fill_nodes(S, P, C, E, tab, kNF, -kPi, -kPi, kTwoPi);
-  eval_rect<NT>(S, P, kNF, 0, 0, kPi * kPi / (4.0 * kPi * kPi));
-  double key = store_region(S, P, s, 0, make_code(0, 0, 0));
+  __syncthreads();
+  fill_nodes<L>(S, P, C, E, tab, kNF, -kPi, -kPi, kTwoPi);
+  if (GRAM == PAID_GRAM_SEPARABLE) sep_stage1<L>(S, kNF, 1);
+  eval_rect<L, GRAM>(S, P, pidmap, kNF, 0, 0, kPi * kPi / (4.0 * kPi * kPi));
+  double key = store_region<L>(S, P, s, 0, make_code(0, 0, 0));
   for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
     P.val[(long)s * P.MU + pid] = S.cq[pid];
     if (P.errp) P.errp[(long)s * P.MU + pid] = (double)(float)fabs(S.ce[pid]);
@@ -258,83 +394,128 @@ __global__ void __launch_bounds__(64) k_root(Problem P) {
 }
 
 // ---------------------------------------------------------------- children
-template <int NT>
-__global__ void __launch_bounds__(64) k_children(Problem P) {
-  extern __shared__ double lds_raw[];
-  WaveLds &S = *reinterpret_cast<WaveLds *>(lds_raw);
-  const int lane = threadIdx.x;
-  const int total = P.counters[2];
+// slot of a work item: woff is an exclusive prefix over slots
+__device__ inline int item_slot(const Problem &P, int w) {
+  int lo = 0, hi = P.W;  // woff[lo] <= w < woff[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (P.woff[mid] <= w) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <int L, int GRAM>
+__device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int w,
+                        const double *tab) {
+  // the pool and the deltas hold P.MU form-factor pairs (<= the box pairs)
+  constexpr int KMAX = (Dims<L>::MU + 63) / 64;
+  const int MU = P.MU;
+  const int lane = lane_id();
+  const int s = item_slot(P, w), r = w - P.woff[s];
+  const long leaf = P.sel[(long)s * P.bmax + r];
+  const long nold = P.nleaf[s];
+  const long pbase = (long)s * P.cap + leaf;
+  const uint64_t pc = P.code[pbase];
+  const double pkey = P.key[pbase];
+  const Ctr C = P.ctr[P.cid[s]];
+  const Entry E = P.entries[C.entry];
+  // delta of the container sums: minus the parent, plus its children
+  double dv[KMAX], dp[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    int pid = lane + 64 * k;
+    dv[k] = (pid < MU) ? -P.Q[pbase * MU + pid] : 0.0;
+    dp[k] = (pid < MU && P.E) ? -(double)P.E[pbase * MU + pid] : 0.0;
+  }
+  const int d = code_depth(pc);
+  const uint64_t ix = code_ix(pc), iy = code_iy(pc);
+  const double wdt = kTwoPi * ldexp(1.0, -d);
+  const double x0 = -kPi + (double)ix * wdt, y0 = -kPi + (double)iy * wdt;
+  fill_nodes<L>(S, P, C, E, tab, kNX, x0, y0, wdt);
+  if (GRAM == PAID_GRAM_SEPARABLE) sep_stage1<L>(S, kNX, 2);
+  const double fa = (0.25 * wdt) * (0.25 * wdt) / (4.0 * kPi * kPi);
+  double dkey = -pkey;
 #pragma unroll 1
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    // slot of this work item: woff is an exclusive prefix over slots
-    int lo = 0, hi = P.W;  // woff[lo] <= w < woff[hi]
-    while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
-      if (P.woff[mid] <= w) lo = mid; else hi = mid;
-    }
-    const int s = lo, r = w - P.woff[s];
-    const long leaf = P.sel[(long)s * P.bmax + r];
-    const long nold = P.nleaf[s];
-    const long pbase = (long)s * P.cap + leaf;
-    const uint64_t pc = P.code[pbase];
-    const double pkey = P.key[pbase];
-    const Ctr C = P.ctr[P.cid[s]];
-    const Entry E = P.entries[C.entry];
-    const double *tab = P.tab + E.tab_off;
-    // delta of the container sums: minus the parent, plus its children
-    constexpr int KMAX = NT == 1 ? (136 + 63) / 64 : (kMaxMU + 63) / 64;
-    double dv[KMAX], dp[KMAX];
+  for (int ch = 0; ch < 4; ++ch) {
+    int cx = ch & 1, cy = ch >> 1;
+    eval_rect<L, GRAM>(S, P, pidmap, kNX, cx, cy, fa);
+    long ri = (ch == 0) ? leaf : nold + 3L * r + (ch - 1);
+    dkey += store_region<L>(S, P, s, ri, make_code(d + 1, 2 * ix + cx, 2 * iy + cy));
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       int pid = lane + 64 * k;
-      dv[k] = (pid < P.MU) ? -P.Q[pbase * P.MU + pid] : 0.0;
-      dp[k] = (pid < P.MU && P.E) ? -(double)P.E[pbase * P.MU + pid] : 0.0;
-    }
-    const int d = code_depth(pc);
-    const uint64_t ix = code_ix(pc), iy = code_iy(pc);
-    const double wdt = kTwoPi * ldexp(1.0, -d);
-    const double x0 = -kPi + (double)ix * wdt, y0 = -kPi + (double)iy * wdt;
-    fill_nodes(S, P, C, E, tab, kNX, x0, y0, wdt);
-    const double fa = (0.25 * wdt) * (0.25 * wdt) / (4.0 * kPi * kPi);
-    double dkey = -pkey;
-#pragma unroll 1
-    for (int ch = 0; ch < 4; ++ch) {
-      int cx = ch & 1, cy = ch >> 1;
-      eval_rect<NT>(S, P, kNX, 8 * cx, 8 * cy, fa);
-      long ri = (ch == 0) ? leaf : nold + 3L * r + (ch - 1);
-      dkey += store_region(S, P, s, ri, make_code(d + 1, 2 * ix + cx, 2 * iy + cy));
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        int pid = lane + 64 * k;
-        if (pid < P.MU) {
-          dv[k] += S.cq[pid];
-          // the same float-rounded value that is stored and later subtracted,
-          // so the running per-pair error sums carry no rounding residue
-          dp[k] += (double)(float)fabs(S.ce[pid]);
-        }
-      }
-      wave_sync();
-    }
-    const long it = (long)s * P.bmax + r;
-#pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-      int pid = lane + 64 * k;
-      if (pid < P.MU) {
-        P.dv[it * P.MU + pid] = dv[k];
-        if (P.dep) P.dep[it * P.MU + pid] = dp[k];
+      if (pid < MU) {
+        dv[k] += S.cq[pid];
+        // the same float-rounded value that is stored and later subtracted,
+        // so the running per-pair error sums carry no rounding residue
+        dp[k] += (double)(float)fabs(S.ce[pid]);
       }
     }
-    if (lane == 0) {
-      P.de[it] = dkey;
-      if (d + 1 > P.st_depth[s]) atomicMax(&P.st_depth[s], d + 1);
+    wave_sync();
+  }
+  const long it = (long)s * P.bmax + r;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    int pid = lane + 64 * k;
+    if (pid < MU) {
+      P.dv[it * MU + pid] = dv[k];
+      if (P.dep) P.dep[it * MU + pid] = dp[k];
     }
+  }
+  if (lane == 0) {
+    P.de[it] = dkey;
+    if (d + 1 > P.st_depth[s]) atomicMax(&P.st_depth[s], d + 1);
   }
 }
 
-size_t lds_bytes(const Problem &P) {
-  // the general-form-factor scratch sits at the end and is dropped otherwise
-  size_t full = sizeof(WaveLds);
-  return P.ff_identity ? full - 3 * sizeof(double) * kMaxMB * kMaxMB : full;
+// Work items are processed in groups (one per wave); each workgroup takes a
+// contiguous range of groups, so consecutive groups mostly belong to the same
+// container and parameter row and the LDS table is loaded once per range.
+template <int L, int GRAM>
+__global__ void __launch_bounds__(256) k_children(Problem P) {
+  extern __shared__ double lds_raw[];
+  __shared__ int pidmap[Dims<L>::MU];
+  __shared__ int s_loaded, s_need;
+  double *tabl = lds_raw;
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
+  WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw + kTabRowsLds * kTabStride +
+                                                  (size_t)wv * P.lds_wave_doubles);
+  build_pidmap<L>(pidmap, threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0) s_loaded = -1;
+  __syncthreads();
+  const int total = P.counters[2];
+  const int ngroups = (total + nw - 1) / nw;
+  const int gper = (ngroups + gridDim.x - 1) / gridDim.x;
+  const int g0 = blockIdx.x * gper, g1 = min(g0 + gper, ngroups);
+#pragma unroll 1
+  for (int g = g0; g < g1; ++g) {
+    // the parameter row of the group's first item decides the LDS table
+    if (threadIdx.x == 0) {
+      int w0 = g * nw;
+      int e0 = P.ctr[P.cid[item_slot(P, w0)]].entry;
+      s_need = (P.entries[e0].J <= kTabRowsLds) ? e0 : -1;
+    }
+    __syncthreads();
+    const int need = s_need, loaded = s_loaded;
+    if (need >= 0 && need != loaded) {
+      const Entry E0 = P.entries[need];
+      const double *src = P.tab + E0.tab_off;
+      for (int i = threadIdx.x; i < E0.J * kTabStride; i += blockDim.x) tabl[i] = src[i];
+      __syncthreads();
+      if (threadIdx.x == 0) s_loaded = need;
+    }
+    __syncthreads();
+    const int w = g * nw + wv;
+    if (w < total) {
+      int s = item_slot(P, w);
+      int e = P.ctr[P.cid[s]].entry;
+      if (e == s_loaded)
+        do_item<L, GRAM>(S, P, pidmap, w, tabl);
+      else
+        do_item<L, GRAM>(S, P, pidmap, w, P.tab + P.entries[e].tab_off);
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- diagnostics
@@ -346,24 +527,43 @@ __global__ void k_kernel_eval(const Entry *e, const double *tab, int ch, const d
   out[i] = K_eval(E, tab + E.tab_off, ch, a[i], b[i]);
 }
 
-}  // namespace
-
-hipError_t launch_root(const Problem &p, hipStream_t s) {
-  size_t sh = lds_bytes(p);
-  if (p.MB > 16)
-    hipLaunchKernelGGL(k_root<2>, dim3(p.W), dim3(64), sh, s, p);
-  else
-    hipLaunchKernelGGL(k_root<1>, dim3(p.W), dim3(64), sh, s, p);
+template <int L, int GRAM>
+hipError_t launch_root_t(const Problem &p, hipStream_t s) {
+  size_t sh = sizeof(double) * wave_lds_doubles<L>(p.ff_identity);
+  hipLaunchKernelGGL((k_root<L, GRAM>), dim3(p.W), dim3(64), sh, s, p);
   return hipGetLastError();
 }
 
-hipError_t launch_eval(const Problem &p, int grid, hipStream_t s) {
-  size_t sh = lds_bytes(p);
-  if (p.MB > 16)
-    hipLaunchKernelGGL(k_children<2>, dim3(grid), dim3(64), sh, s, p);
-  else
-    hipLaunchKernelGGL(k_children<1>, dim3(grid), dim3(64), sh, s, p);
+template <int L, int GRAM>
+hipError_t launch_eval_t(Problem p, int grid, hipStream_t s) {
+  p.lds_wave_doubles = (int)wave_lds_doubles<L>(p.ff_identity);
+  // as many waves per workgroup (up to 4) as fit in 64 KiB with the table
+  const size_t avail = 65536 - 2048 - sizeof(double) * kTabRowsLds * kTabStride;
+  int waves = (int)(avail / (sizeof(double) * p.lds_wave_doubles));
+  waves = waves < 1 ? 1 : (waves > 4 ? 4 : waves);
+  size_t sh = sizeof(double) * ((size_t)kTabRowsLds * kTabStride + (size_t)waves * p.lds_wave_doubles);
+  hipLaunchKernelGGL((k_children<L, GRAM>), dim3(grid), dim3(64 * waves), sh, s, p);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_root(const Problem &p, hipStream_t s) {
+  const bool sep = p.gram == PAID_GRAM_SEPARABLE;
+  switch (p.L) {
+    case 0: return sep ? launch_root_t<0, 1>(p, s) : launch_root_t<0, 0>(p, s);
+    case 1: return sep ? launch_root_t<1, 1>(p, s) : launch_root_t<1, 0>(p, s);
+    default: return sep ? launch_root_t<2, 1>(p, s) : launch_root_t<2, 0>(p, s);
+  }
+}
+
+hipError_t launch_eval(const Problem &p, int grid, hipStream_t s) {
+  const bool sep = p.gram == PAID_GRAM_SEPARABLE;
+  switch (p.L) {
+    case 0: return sep ? launch_eval_t<0, 1>(p, grid, s) : launch_eval_t<0, 0>(p, grid, s);
+    case 1: return sep ? launch_eval_t<1, 1>(p, grid, s) : launch_eval_t<1, 0>(p, grid, s);
+    default: return sep ? launch_eval_t<2, 1>(p, grid, s) : launch_eval_t<2, 0>(p, grid, s);
+  }
 }
 
 hipError_t launch_kernel_eval(const Entry *e, const double *tab, int ch, const double *a,

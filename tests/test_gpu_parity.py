@@ -25,9 +25,10 @@ def P():
     return P
 
 
-@pytest.fixture(scope="module")
-def ctx(P):
-    c = P.Context(max_regions=1 << 16, max_active=512)
+@pytest.fixture(scope="module", params=["separable", "mfma"])
+def ctx(P, request):
+    gram = P.GRAM_SEPARABLE if request.param == "separable" else P.GRAM_MFMA
+    c = P.Context(max_regions=1 << 16, max_active=512, gram=gram)
     yield c
     c.close()
 
