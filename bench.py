@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--variants", action="store_true", help="also time one call per flow scale")
     ap.add_argument("--gram", choices=["separable", "mfma"], default="separable")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
+                    help="arithmetic of the matrix-core projection (with --gram mfma)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (the reference "
                          "for scaling the HBM byte counters) and exit")
@@ -122,7 +124,8 @@ def main():
     n_int = n_ctr * MU
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    ctx = P.Context(stream=stream.cuda_stream, profile=1,
+    prec = {"fp64": P.FP64, "fp32": P.FP32, "bf16x3": P.BF16X3}[args.precision]
+    ctx = P.Context(stream=stream.cuda_stream, profile=1, precision=prec,
                     gram=P.GRAM_SEPARABLE if args.gram == "separable" else P.GRAM_MFMA)
     out = torch.empty((len(params), len(q), nch, M, M), dtype=torch.float64, device=dev)
     run = lambda o: ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=o)
@@ -161,7 +164,8 @@ def main():
 
     line = {"metric": METRIC, "value": value, "unit": "integrals/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if args.precision == "fp64" else f"{args.precision} projection, f64 sums",
             "data": "synthetic",
             "config": {"workload": f"{cfg['name']}: {cfg['desc']}", "containers": n_ctr,
                        "integrals_per_step": n_int, "variant": "batched (all containers in one "

@@ -275,7 +275,10 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
     return fail(nullptr, PAID_EINVAL, "need 1 <= batch <= batch_max");
   if (cfg.err_mode != PAID_ERR_GLOBAL && cfg.err_mode != PAID_ERR_PER_INTEGRAL)
     return fail(nullptr, PAID_EINVAL, "bad err_mode");
-  if (cfg.precision != PAID_FP64) return fail(nullptr, PAID_EINVAL, "precision mode not built");
+  if (cfg.precision != PAID_FP64 && cfg.precision != PAID_FP32 && cfg.precision != PAID_BF16X3)
+    return fail(nullptr, PAID_EINVAL, "bad precision");
+  if (cfg.precision != PAID_FP64 && cfg.gram != PAID_GRAM_MFMA)
+    return fail(nullptr, PAID_EINVAL, "reduced precision needs the matrix-core projection");
   if (cfg.gram != PAID_GRAM_MFMA && cfg.gram != PAID_GRAM_SEPARABLE)
     return fail(nullptr, PAID_EINVAL, "bad gram mode");
   if (cfg.kind < 0 || cfg.kind > 3) return fail(nullptr, PAID_EINVAL, "bad kind");
@@ -650,6 +653,7 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
   P.n_ctr = 1;
   P.kind = cfg.kind;
   P.err_mode = PAID_ERR_GLOBAL;
+  P.precision = cfg.precision;
   P.gram = cfg.gram;
   P.gauss_x = cfg.gauss[0];
   P.gauss_y = cfg.gauss[1];

@@ -87,6 +87,37 @@ __device__ inline int prod_index(int a, int c) {  // (a, c) -> index of u_a u_c
   return a * NB - a * (a - 1) / 2 + (c - a);
 }
 
+// sin and cos of |x| <= pi (+ rounding): reduction by pi/2 in two parts
+// (Cody-Waite; q*pi/2 is exact for |q| <= 2) to |r| <= pi/4, then the Taylor
+// series of sin and cos to degree 17/18 (truncation below 1e-19 there).
+__device__ inline void sincos_zone(double x, double *s, double *c) {
+  const double pio2_hi = 1.5707963267948966, pio2_lo = 6.123233995736766e-17;
+  const double q = rint(x * 0.63661977236758134);
+  const double r = (x - q * pio2_hi) - q * pio2_lo, r2 = r * r;
+  double ps = 1.0 / 355687428096000.0;  // 1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);
+  ps = fma(ps, r2, 1.0 / 6227020800.0);
+  ps = fma(ps, r2, -1.0 / 39916800.0);
+  ps = fma(ps, r2, 1.0 / 362880.0);
+  ps = fma(ps, r2, -1.0 / 5040.0);
+  ps = fma(ps, r2, 1.0 / 120.0);
+  ps = fma(ps, r2, -1.0 / 6.0);
+  const double sr = fma(ps * r2, r, r);
+  double pc = 1.0 / 6402373705728000.0;  // 1/18!
+  pc = fma(pc, r2, -1.0 / 20922789888000.0);
+  pc = fma(pc, r2, 1.0 / 87178291200.0);
+  pc = fma(pc, r2, -1.0 / 479001600.0);
+  pc = fma(pc, r2, 1.0 / 3628800.0);
+  pc = fma(pc, r2, -1.0 / 40320.0);
+  pc = fma(pc, r2, 1.0 / 720.0);
+  pc = fma(pc, r2, -1.0 / 24.0);
+  pc = fma(pc, r2, 0.5);
+  const double cr = fma(-pc, r2, 1.0);
+  const int k = ((int)q) & 3;
+  *s = (k == 0) ? sr : (k == 1) ? cr : (k == 2) ? -sr : -cr;
+  *c = (k == 0) ? cr : (k == 1) ? -sr : (k == 2) ? -cr : sr;
+}
+
 // Coordinates of one axis: nco = 17 (four children of a rectangle of width
 // wdt starting at x0) or 9 (a single rectangle).
 __device__ inline double axis_coord(int j, int nco, double x0, double wdt) {
@@ -106,7 +137,7 @@ __device__ void fill_nodes(WaveLds<L> &S, const Problem &P, const Ctr &C, const 
     int ax = lane >= nco, j = lane - ax * nco;
     double p = axis_coord(j, nco, ax ? y0 : x0, wdt);
     double sp, cpp;
-    sincos(p, &sp, &cpp);
+    sincos_zone(p, &sp, &cpp);
     double cL = ax ? C.cLy : C.cLx, sL = ax ? C.sLy : C.sLx;
     S.pos[ax][j] = p;
     S.cp[ax][j] = cL * cpp - sL * sp;  // cos(l/2 + p)
@@ -214,66 +245,183 @@ __device__ void sep_stage2(WaveLds<L> &S, const Problem &P, const int *pidmap, i
 }
 
 // ------------------------------------------------------------- dense MFMA
-// Weighted Gram of one rectangle on the FP64 matrix cores.  Its 9 x 9 nodes
-// are rows offx.. and columns offy.. of the nco x nco grid.
+// Weighted Gram of one rectangle on the matrix cores.  Its 9 x 9 nodes are
+// rows offx.. and columns offy.. of the nco x nco grid.  A row of A is a box
+// function times w g (fine weights for Q_2N, w_2N - w_N for E, which keeps the
+// error estimate free of a rounding floor in reduced precision), B is the box
+// function; results are scaled by fa and widened to FP64.
+
+// one product term of the Gram at a node: values for this lane's A and B
+struct GramVals {
+  double aq0, ae0, b0, aq1, ae1, b1;
+};
+
 template <int L>
+__device__ inline GramVals gram_node_vals(const WaveLds<L> &S, int nu, int nco, int offx, int offy,
+                                         bool v0, bool v1, int a0, int b0, int a1, int b1) {
+  GramVals r = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (nu < kNF * kNF) {
+    int a = nu / kNF, b = nu - a * kNF;
+    int gx = offx + a, gy = offy + b;
+    double g = S.g[gx * nco + gy];
+    double w2 = c_rule.w2[a] * c_rule.w2[b];
+    double wn = ((a | b) & 1) ? 0.0 : c_rule.w1[a >> 1] * c_rule.w1[b >> 1];
+    double gq = g * w2, ge = g * (w2 - wn);
+    if (v0) {
+      r.b0 = S.u[0][gx][a0] * S.u[1][gy][b0];
+      r.aq0 = r.b0 * gq;
+      r.ae0 = r.b0 * ge;
+    }
+    if (v1) {
+      r.b1 = S.u[0][gx][a1] * S.u[1][gy][b1];
+      r.aq1 = r.b1 * gq;
+      r.ae1 = r.b1 * ge;
+    }
+  }
+  return r;
+}
+
+// store the accumulated tiles: element (i, j) of tile t
+template <int L>
+__device__ inline void gram_put(WaveLds<L> &S, const Problem &P, int i, int j, double q, double e) {
+  constexpr int MB = Dims<L>::MB;
+  if (i < MB && j < MB && i <= j) {
+    if (P.ff_identity) {
+      int pid = pair_index(i, j, MB);
+      S.cq[pid] = q;
+      S.ce[pid] = e;
+    } else {
+      S.tq[i * MB + j] = q;
+      S.tq[j * MB + i] = q;
+      S.ts[i * MB + j] = e;
+      S.ts[j * MB + i] = e;
+    }
+  }
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+// three-term bf16 split x = hi + mid + lo (8 significant bits each)
+__device__ inline void split3(double x, __bf16 &hi, __bf16 &mid, __bf16 &lo) {
+  float f = (float)x;
+  hi = (__bf16)f;
+  float r1 = f - (float)hi;
+  mid = (__bf16)r1;
+  lo = (__bf16)(r1 - (float)mid);
+}
+
+template <int L, int PREC>
 __device__ void gram_mfma(WaveLds<L> &S, const Problem &P, int nco, int offx, int offy, double fa) {
   constexpr int NB = Dims<L>::NB, MB = Dims<L>::MB, NT = MB > 16 ? 2 : 1;
+  constexpr int NACC = NT * (NT + 1) / 2;
   const int lane = lane_id(), m = lane & 15, kk = lane >> 4;
   const bool v0 = m < MB, v1 = (NT == 2) && (m + 16 < MB);
   const int a0 = v0 ? m / NB : 0, b0 = v0 ? m % NB : 0;
   const int a1 = v1 ? (m + 16) / NB : 0, b1 = v1 ? (m + 16) % NB : 0;
-  constexpr int NACC = NT * (NT + 1) / 2;
-  d4 aq[NACC], ae[NACC];
+  if (PREC == PAID_FP64) {
+    d4 aq[NACC], ae[NACC];
 #pragma unroll
-  for (int t = 0; t < NACC; ++t) {
-    aq[t] = d4{0.0, 0.0, 0.0, 0.0};
-    ae[t] = d4{0.0, 0.0, 0.0, 0.0};
-  }
+    for (int t = 0; t < NACC; ++t) {
+      aq[t] = d4{0.0, 0.0, 0.0, 0.0};
+      ae[t] = d4{0.0, 0.0, 0.0, 0.0};
+    }
 #pragma unroll 3
-  for (int kb = 0; kb < 21; ++kb) {
-    int nu = 4 * kb + kk;
-    double u0 = 0.0, u1 = 0.0, gq = 0.0, ge = 0.0;
-    if (nu < kNF * kNF) {
-      int a = nu / kNF, b = nu - a * kNF;
-      int gx = offx + a, gy = offy + b;
-      double g = S.g[gx * nco + gy];
-      double w2 = c_rule.w2[a] * c_rule.w2[b];
-      double wn = ((a | b) & 1) ? 0.0 : c_rule.w1[a >> 1] * c_rule.w1[b >> 1];
-      gq = g * w2;
-      ge = g * (w2 - wn);
-      if (v0) u0 = S.u[0][gx][a0] * S.u[1][gy][b0];
-      if (v1) u1 = S.u[0][gx][a1] * S.u[1][gy][b1];
+    for (int kb = 0; kb < 21; ++kb) {
+      GramVals v = gram_node_vals<L>(S, 4 * kb + kk, nco, offx, offy, v0, v1, a0, b0, a1, b1);
+      aq[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.aq0, v.b0, aq[0], 0, 0, 0);
+      ae[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.ae0, v.b0, ae[0], 0, 0, 0);
+      if (NT == 2) {
+        aq[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.aq0, v.b1, aq[1], 0, 0, 0);
+        ae[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.ae0, v.b1, ae[1], 0, 0, 0);
+        aq[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.aq1, v.b1, aq[2], 0, 0, 0);
+        ae[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.ae1, v.b1, ae[2], 0, 0, 0);
+      }
     }
-    aq[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(u0 * gq, u0, aq[0], 0, 0, 0);
-    ae[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(u0 * ge, u0, ae[0], 0, 0, 0);
-    if (NT == 2) {
-      aq[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(u0 * gq, u1, aq[1], 0, 0, 0);
-      ae[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(u0 * ge, u1, ae[1], 0, 0, 0);
-      aq[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(u1 * gq, u1, aq[2], 0, 0, 0);
-      ae[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(u1 * ge, u1, ae[2], 0, 0, 0);
+    // f64 16x16x4 result: row = 4 r + lane >> 4, col = lane & 15
+#pragma unroll
+    for (int t = 0; t < NACC; ++t) {
+      int tr = (NT == 2 && t == 2) ? 1 : 0, tc = (NT == 2 && t >= 1) ? 1 : 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        gram_put<L>(S, P, 16 * tr + 4 * r + kk, 16 * tc + m, fa * aq[t][r], fa * ae[t][r]);
     }
-  }
-  // result lane layout of the f64 16x16x4 tile: row = 4 r + lane >> 4, col = lane & 15
+  } else if (PREC == PAID_FP32) {
+    f4v aq[NACC], ae[NACC];
 #pragma unroll
-  for (int t = 0; t < NACC; ++t) {
-    int tr = (NT == 2 && t == 2) ? 1 : 0, tc = (NT == 2 && t >= 1) ? 1 : 0;
+    for (int t = 0; t < NACC; ++t) {
+      aq[t] = f4v{0.f, 0.f, 0.f, 0.f};
+      ae[t] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll 3
+    for (int kb = 0; kb < 21; ++kb) {
+      GramVals v = gram_node_vals<L>(S, 4 * kb + kk, nco, offx, offy, v0, v1, a0, b0, a1, b1);
+      aq[0] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)v.aq0, (float)v.b0, aq[0], 0, 0, 0);
+      ae[0] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)v.ae0, (float)v.b0, ae[0], 0, 0, 0);
+      if (NT == 2) {
+        aq[1] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)v.aq0, (float)v.b1, aq[1], 0, 0, 0);
+        ae[1] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)v.ae0, (float)v.b1, ae[1], 0, 0, 0);
+        aq[2] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)v.aq1, (float)v.b1, aq[2], 0, 0, 0);
+        ae[2] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)v.ae1, (float)v.b1, ae[2], 0, 0, 0);
+      }
+    }
+    // f32 16x16x4 result: row = 4 (lane >> 4) + r, col = lane & 15
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int i = 16 * tr + 4 * r + kk, j = 16 * tc + m;
-      if (i < MB && j < MB && i <= j) {
-        double q = fa * aq[t][r], e = fa * ae[t][r];
-        if (P.ff_identity) {
-          int pid = pair_index(i, j, MB);
-          S.cq[pid] = q;
-          S.ce[pid] = e;
-        } else {
-          S.tq[i * MB + j] = q;
-          S.tq[j * MB + i] = q;
-          S.ts[i * MB + j] = e;
-          S.ts[j * MB + i] = e;
+    for (int t = 0; t < NACC; ++t) {
+      int tr = (NT == 2 && t == 2) ? 1 : 0, tc = (NT == 2 && t >= 1) ? 1 : 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        gram_put<L>(S, P, 16 * tr + 4 * kk + r, 16 * tc + m, fa * (double)aq[t][r],
+                    fa * (double)ae[t][r]);
+    }
+  } else {  // three-term bf16 split, 16x16x32 tiles, FP32 accumulation
+    f4v aq[NACC], ae[NACC];
+#pragma unroll
+    for (int t = 0; t < NACC; ++t) {
+      aq[t] = f4v{0.f, 0.f, 0.f, 0.f};
+      ae[t] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll 1
+    for (int kb = 0; kb < 3; ++kb) {
+      // this lane: row/col m, nodes 32 kb + 8 kk + e, e = 0..7
+      bf8v q0[3], e0[3], c0[3], q1[3], e1[3], c1[3];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        GramVals v = gram_node_vals<L>(S, 32 * kb + 8 * kk + e, nco, offx, offy, v0, v1, a0, b0,
+                                       a1, b1);
+        __bf16 h, md, lo;
+        split3(v.aq0, h, md, lo); q0[0][e] = h; q0[1][e] = md; q0[2][e] = lo;
+        split3(v.ae0, h, md, lo); e0[0][e] = h; e0[1][e] = md; e0[2][e] = lo;
+        split3(v.b0, h, md, lo); c0[0][e] = h; c0[1][e] = md; c0[2][e] = lo;
+        if (NT == 2) {
+          split3(v.aq1, h, md, lo); q1[0][e] = h; q1[1][e] = md; q1[2][e] = lo;
+          split3(v.ae1, h, md, lo); e1[0][e] = h; e1[1][e] = md; e1[2][e] = lo;
+          split3(v.b1, h, md, lo); c1[0][e] = h; c1[1][e] = md; c1[2][e] = lo;
         }
       }
+      // A B ~ hi hi + hi mid + mid hi + hi lo + lo hi + mid mid (terms >= 2^-16)
+      const int ia[6] = {0, 0, 1, 0, 2, 1}, ib[6] = {0, 1, 0, 2, 0, 1};
+#pragma unroll
+      for (int t6 = 0; t6 < 6; ++t6) {
+        const int x = ia[t6], y = ib[t6];
+        aq[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q0[x], c0[y], aq[0], 0, 0, 0);
+        ae[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(e0[x], c0[y], ae[0], 0, 0, 0);
+        if (NT == 2) {
+          aq[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q0[x], c1[y], aq[1], 0, 0, 0);
+          ae[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(e0[x], c1[y], ae[1], 0, 0, 0);
+          aq[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(q1[x], c1[y], aq[2], 0, 0, 0);
+          ae[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(e1[x], c1[y], ae[2], 0, 0, 0);
+        }
+      }
+    }
+    // bf16 16x16x32 result: row = 4 (lane >> 4) + r, col = lane & 15
+#pragma unroll
+    for (int t = 0; t < NACC; ++t) {
+      int tr = (NT == 2 && t == 2) ? 1 : 0, tc = (NT == 2 && t >= 1) ? 1 : 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        gram_put<L>(S, P, 16 * tr + 4 * kk + r, 16 * tc + m, fa * (double)aq[t][r],
+                    fa * (double)ae[t][r]);
     }
   }
   wave_sync();
@@ -335,13 +483,17 @@ __device__ double store_region(WaveLds<L> &S, const Problem &P, int s, long ri, 
 
 // One rectangle of the grid (child (cx, cy) of the 17-grid, or the 9-grid
 // root with cx = cy = 0): fills S.cq / S.ce.
+// GRAM: 0..2 = dense Gram on the matrix cores in FP64 / FP32 / bf16x3,
+// 3 = separable FP64
+constexpr int kSep = 3;
+
 template <int L, int GRAM>
 __device__ void eval_rect(WaveLds<L> &S, const Problem &P, const int *pidmap, int nco, int cx,
                           int cy, double fa) {
-  if (GRAM == PAID_GRAM_SEPARABLE) {
+  if (GRAM == kSep) {
     sep_stage2<L>(S, P, pidmap, cx, cy, fa);
   } else {
-    gram_mfma<L>(S, P, nco, 8 * cx, 8 * cy, fa);
+    gram_mfma<L, GRAM>(S, P, nco, 8 * cx, 8 * cy, fa);
   }
   if (!P.ff_identity) transform_ff<L>(S, P);
 }
@@ -375,7 +527,7 @@ __global__ void __launch_bounds__(64) k_root(Problem P) {
   for (int pid = threadIdx.x; pid < P.MU; pid += 64) P.itau[(long)s * P.MU + pid] = 1.0f;
   __syncthreads();
   fill_nodes<L>(S, P, C, E, tab, kNF, -kPi, -kPi, kTwoPi);
-  if (GRAM == PAID_GRAM_SEPARABLE) sep_stage1<L>(S, kNF, 1);
+  if (GRAM == kSep) sep_stage1<L>(S, kNF, 1);
   eval_rect<L, GRAM>(S, P, pidmap, kNF, 0, 0, kPi * kPi / (4.0 * kPi * kPi));
   double key = store_region<L>(S, P, s, 0, make_code(0, 0, 0));
   for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
@@ -432,7 +584,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int 
   const double wdt = kTwoPi * ldexp(1.0, -d);
   const double x0 = -kPi + (double)ix * wdt, y0 = -kPi + (double)iy * wdt;
   fill_nodes<L>(S, P, C, E, tab, kNX, x0, y0, wdt);
-  if (GRAM == PAID_GRAM_SEPARABLE) sep_stage1<L>(S, kNX, 2);
+  if (GRAM == kSep) sep_stage1<L>(S, kNX, 2);
   const double fa = (0.25 * wdt) * (0.25 * wdt) / (4.0 * kPi * kPi);
   double dkey = -pkey;
 #pragma unroll 1
@@ -477,7 +629,9 @@ __global__ void __launch_bounds__(256) k_children(Problem P) {
   __shared__ int pidmap[Dims<L>::MU];
   __shared__ int s_loaded, s_need;
   double *tabl = lds_raw;
-  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6;
+  // the wave index is uniform in a wave: keep it (and all per-item
+  // bookkeeping derived from it) in scalar registers
+  const int nw = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw + kTabRowsLds * kTabStride +
                                                   (size_t)wv * P.lds_wave_doubles);
   build_pidmap<L>(pidmap, threadIdx.x, blockDim.x);
@@ -548,21 +702,45 @@ hipError_t launch_eval_t(Problem p, int grid, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+// projection/precision mode of a problem: separable FP64, or the dense Gram
+// in the requested precision
+int gram_mode(const Problem &p) { return p.gram == PAID_GRAM_SEPARABLE ? kSep : p.precision; }
+
+template <int L>
+hipError_t launch_root_l(const Problem &p, hipStream_t s) {
+  switch (gram_mode(p)) {
+    case kSep: return launch_root_t<L, kSep>(p, s);
+    case PAID_FP32: return launch_root_t<L, PAID_FP32>(p, s);
+    case PAID_BF16X3: return launch_root_t<L, PAID_BF16X3>(p, s);
+    default: return launch_root_t<L, PAID_FP64>(p, s);
+  }
+}
+
+template <int L>
+hipError_t launch_eval_l(const Problem &p, int grid, hipStream_t s) {
+  switch (gram_mode(p)) {
+    case kSep: return launch_eval_t<L, kSep>(p, grid, s);
+    case PAID_FP32: return launch_eval_t<L, PAID_FP32>(p, grid, s);
+    case PAID_BF16X3: return launch_eval_t<L, PAID_BF16X3>(p, grid, s);
+    default: return launch_eval_t<L, PAID_FP64>(p, grid, s);
+  }
+}
+}  // namespace
+
 hipError_t launch_root(const Problem &p, hipStream_t s) {
-  const bool sep = p.gram == PAID_GRAM_SEPARABLE;
   switch (p.L) {
-    case 0: return sep ? launch_root_t<0, 1>(p, s) : launch_root_t<0, 0>(p, s);
-    case 1: return sep ? launch_root_t<1, 1>(p, s) : launch_root_t<1, 0>(p, s);
-    default: return sep ? launch_root_t<2, 1>(p, s) : launch_root_t<2, 0>(p, s);
+    case 0: return launch_root_l<0>(p, s);
+    case 1: return launch_root_l<1>(p, s);
+    default: return launch_root_l<2>(p, s);
   }
 }
 
 hipError_t launch_eval(const Problem &p, int grid, hipStream_t s) {
-  const bool sep = p.gram == PAID_GRAM_SEPARABLE;
   switch (p.L) {
-    case 0: return sep ? launch_eval_t<0, 1>(p, grid, s) : launch_eval_t<0, 0>(p, grid, s);
-    case 1: return sep ? launch_eval_t<1, 1>(p, grid, s) : launch_eval_t<1, 0>(p, grid, s);
-    default: return sep ? launch_eval_t<2, 1>(p, grid, s) : launch_eval_t<2, 0>(p, grid, s);
+    case 0: return launch_eval_l<0>(p, grid, s);
+    case 1: return launch_eval_l<1>(p, grid, s);
+    default: return launch_eval_l<2>(p, grid, s);
   }
 }
 

@@ -28,7 +28,7 @@ def P():
 @pytest.fixture(scope="module", params=["separable", "mfma"])
 def ctx(P, request):
     gram = P.GRAM_SEPARABLE if request.param == "separable" else P.GRAM_MFMA
-    c = P.Context(max_regions=1 << 16, max_active=512, gram=gram)
+    c = P.Context(max_regions=1 << 16, max_active=512, gram=gram)  # FP64 either way
     yield c
     c.close()
 
@@ -247,3 +247,50 @@ def test_full_size_workload_sampled(P):
         assert gate_ratio(out[ip, iq, ch], ref[k], 1e-6) <= 1.0, (ip, iq, ch)
     # symmetry of every output matrix
     assert np.array_equal(out, np.swapaxes(out, -1, -2))
+
+
+# ------------------------------------------------------------------ reduced precision
+# The dense Gram in FP32 or with three-term bf16 splits (FP32 accumulation)
+# carries ~2^-24 relative error per product; region sums, the error estimate
+# and the termination test stay FP64.  Stated tolerance of these modes: every
+# rectangle within 2e-6 of its largest entry, every integral within the gate
+# at rtol 2e-5 (observed values are printed).
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("ff_name", ["ff9", "ff25"])
+def test_reduced_precision_rectangles(P, prec, ff_name):
+    ff, L = (W.ff_box(1), 1) if ff_name == "ff9" else (W.ff_box(2), 2)
+    pr = P.FP32 if prec == "fp32" else P.BF16X3
+    row = (1.0, -0.3, -1.1, 0.02, 0.05)
+    l = (2.88, 0.26)
+    codes = np.array([(0, 0, 0), (2, 1, 3), (6, 17, 40), (10, 700, 12)])
+    with P.Context(gram=P.GRAM_MFMA, precision=pr) as c:
+        q2n, keys = c.children(row, l, P.PH, ff, L, codes)
+    oc = O.Container(ff, L, t=row[0], tp=row[1], mu=row[2], T=row[3], Omega=row[4], lx=l[0],
+                     ly=l[1], channel=O.PH)
+    worst = 0.0
+    for i, (d, ix, iy) in enumerate(codes):
+        w = 2 * math.pi / 2 ** d
+        for k in range(4):
+            x0 = -math.pi + ix * w + (k & 1) * w / 2
+            y0 = -math.pi + iy * w + (k >> 1) * w / 2
+            qn, ref = oc.region(x0, x0 + w / 2, y0, y0 + w / 2)
+            worst = max(worst, np.abs(q2n[i, k] - ref).max() / np.abs(ref).max())
+    print(f"{prec} {ff_name}: worst rectangle error {worst:.2e} of the largest entry")
+    assert worst <= 2e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_reduced_precision_integrals(P, prec):
+    pr = P.FP32 if prec == "fp32" else P.BF16X3
+    p = np.array([[1.0, -0.3, -1.1, 0.05, 0.3]])
+    q = np.array([[2.88, 0.26], [0.0, 0.0], [1.0, -2.0]])
+    ff, L = W.ff_box(2), 2
+    with P.Context(gram=P.GRAM_MFMA, precision=pr, max_regions=1 << 16) as c:
+        out, _, st, rc = c.integrate(p, q, ff, L, rtol=1e-6)
+    assert rc == P.OK
+    cfg = dict(params=p, q=q, ff=ff, L=L, channels=3)
+    ref = oracle_refs(cfg, W.containers(cfg), 1e-9)
+    worst = max(gate_ratio(out[ip, iq, c], ref[k], 1.0)
+                for k, (ip, iq, c) in enumerate(W.containers(cfg)))
+    print(f"{prec}: worst integral error {worst:.2e} (gate units of rtol = 1)")
+    assert worst <= 2e-5
