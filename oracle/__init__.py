@@ -88,6 +88,18 @@ def lib():
         L.po_integrate_batch.argtypes = [C.POINTER(Problem), C.c_int, C.POINTER(Options),
                                          dp, dp, C.POINTER(Stats), C.c_int]
         L.po_brute.argtypes = [C.POINTER(Problem), C.c_int, dp]
+        L.po_mlp_nparams.restype = C.c_long
+        L.po_mlp_forward.argtypes = [dp, dp, C.c_int, dp]
+        L.po_mlp_loss_grad.argtypes = [dp, dp, dp, C.c_int, dp]
+        L.po_mlp_loss_grad.restype = C.c_double
+        L.po_mlp_adam.argtypes = [dp, dp, dp, dp, C.c_long, C.c_int, C.c_double]
+        ip = C.POINTER(C.c_int)
+        L.po_seed_features.argtypes = [C.c_double] * 7 + [C.c_int, dp, ip]
+        L.po_tree_labels.argtypes = [dp, C.c_long, dp]
+        L.po_integrate_labels.argtypes = [C.POINTER(Problem), C.POINTER(Options), dp, dp,
+                                          C.POINTER(Stats), dp]
+        L.po_seed_tree.argtypes = [dp, C.c_int, C.c_double, C.c_long, dp, ip]
+        L.po_seed_tree.restype = C.c_long
         _lib = L
     return _lib
 
@@ -150,6 +162,21 @@ class Container:
             raise ValueError("bad problem")
         return qn, q2n
 
+    def integrate_labels(self, rtol=1e-6, atol=0.0, N=4, err_mode=ERR_GLOBAL, batch=1,
+                         nu=1e-3, max_regions=1 << 22):
+        """Mode-B integration that also returns the 16x16 labels of the final
+        tree (container frame, index 16*j + i)."""
+        v = np.zeros((self.M, self.M))
+        e = np.zeros((self.M, self.M))
+        y = np.zeros(256)
+        st = Stats()
+        o = Options(N, MODE_B, err_mode, batch, rtol, atol, nu, max_regions)
+        rc = lib().po_integrate_labels(C.byref(self.s), C.byref(o), _dp(v), _dp(e), C.byref(st),
+                                       _dp(y))
+        if rc < 0:
+            raise ValueError("bad problem or options")
+        return v, e, st.as_dict(), y
+
     def brute(self, L: int) -> np.ndarray:
         v = np.zeros((self.M, self.M))
         if lib().po_brute(C.byref(self.s), L, _dp(v)) != 0:
@@ -187,3 +214,61 @@ def integrate_batch(containers, rtol=1e-6, atol=0.0, N=4, mode=MODE_B,
     if rc < 0:
         raise ValueError("bad problem or options")
     return vals, errs, [s.as_dict() for s in sts], rc
+
+
+# ---------------------------------------------------------------- density model
+MLP_IN, MLP_HID, MLP_OUT = 7, 128, 256
+
+
+def mlp_nparams() -> int:
+    return lib().po_mlp_nparams()
+
+
+def mlp_forward(w, x):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_IN)
+    y = np.zeros((x.shape[0], MLP_OUT))
+    lib().po_mlp_forward(_dp(w), _dp(x), x.shape[0], _dp(y))
+    return y
+
+
+def mlp_loss_grad(w, x, y):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_IN)
+    y = np.ascontiguousarray(y, dtype=np.float64).reshape(-1, MLP_OUT)
+    g = np.zeros_like(w)
+    loss = lib().po_mlp_loss_grad(_dp(w), _dp(x), _dp(y), x.shape[0], _dp(g))
+    return loss, g
+
+
+def mlp_adam(w, g, m, v, t, lr):
+    """in place on w, m, v (float64 arrays)"""
+    lib().po_mlp_adam(_dp(w), _dp(g), _dp(m), _dp(v), w.size, t, lr)
+
+
+# ---------------------------------------------------------------- seeding
+def seed_features(t, tp, mu, T, Omega, lx, ly, channel):
+    """(features[7], cellmap[256]): model inputs and, per container cell,
+    the model cell it reads."""
+    x = np.zeros(7)
+    cm = np.zeros(256, dtype=np.int32)
+    lib().po_seed_features(t, tp, mu, T, Omega, lx, ly, channel, _dp(x),
+                           cm.ctypes.data_as(C.POINTER(C.c_int)))
+    return x, cm
+
+
+def tree_labels(rects):
+    r = np.ascontiguousarray(rects, dtype=np.float64).reshape(-1, 4)
+    y = np.zeros(256)
+    lib().po_tree_labels(_dp(r), r.shape[0], _dp(y))
+    return y
+
+
+def seed_tree(count, dmax, thresh, limit):
+    """(n_leaves, rects [n][4], depth bound used)"""
+    cnt = np.ascontiguousarray(count, dtype=np.float64)
+    d = C.c_int(0)
+    n = lib().po_seed_tree(_dp(cnt), dmax, thresh, limit, None, C.byref(d))
+    rects = np.zeros((max(n, 1), 4))
+    lib().po_seed_tree(_dp(cnt), dmax, thresh, limit, _dp(rects), C.byref(d))
+    return n, rects[:n], d.value

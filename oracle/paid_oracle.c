@@ -503,8 +503,22 @@ static double po_key(const po_options *o, int np, int pair, const double *err,
   return k;
 }
 
+static int po_integrate_impl(const po_problem *pr, const po_options *o, double *value,
+                             double *errout, po_stats *st, double *labels);
+
 int po_integrate(const po_problem *pr, const po_options *o, double *value, double *errout,
                  po_stats *st) {
+  return po_integrate_impl(pr, o, value, errout, st, NULL);
+}
+
+int po_integrate_labels(const po_problem *pr, const po_options *o, double *value, double *err,
+                        po_stats *st, double labels[256]) {
+  if (!labels || !o || o->mode != PO_MODE_B) return -2;
+  return po_integrate_impl(pr, o, value, err, st, labels);
+}
+
+static int po_integrate_impl(const po_problem *pr, const po_options *o, double *value,
+                             double *errout, po_stats *st, double *labels) {
   if (!pr || !o || !value || o->batch < 1 || !(o->rtol >= 0) || !(o->atol >= 0) ||
       (o->rtol <= 0 && o->atol <= 0) || o->max_regions < 1)
     return -2;
@@ -621,6 +635,15 @@ int po_integrate(const po_problem *pr, const po_options *o, double *value, doubl
   }
   S.regions = h.n;
   S.kernel_evals = c.kernel_evals;
+  if (labels) {
+    long nl = 0;
+    double *rl = (double *)malloc(sizeof(double) * 4 * (s.n > 0 ? s.n : 1));
+    if (!rl) goto done;
+    for (long i = 0; i < s.n; ++i)
+      if (s.leaf[i]) memcpy(&rl[4 * nl++], &s.geo[4 * i], 4 * sizeof(double));
+    po_tree_labels(rl, nl, labels);
+    free(rl);
+  }
   rc = S.converged ? 0 : 1;
 done:
   if (st) *st = S;
@@ -684,4 +707,204 @@ int po_brute(const po_problem *pr, int L, double *value) {
   free(acc);
   po_msum_free(&m);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Subdivision-density model: plain FP64 multilayer perceptron.              */
+static const int po_dims[5] = {PO_MLP_IN, PO_MLP_HID, PO_MLP_HID, PO_MLP_HID, PO_MLP_OUT};
+
+long po_mlp_nparams(void) {
+  long n = 0;
+  for (int l = 0; l < 4; ++l) n += (long)po_dims[l + 1] * po_dims[l] + po_dims[l + 1];
+  return n;
+}
+
+static double po_gelu(double z) { return 0.5 * z * (1.0 + erf(z / sqrt(2.0))); }
+static double po_gelu_d(double z) {
+  return 0.5 * (1.0 + erf(z / sqrt(2.0))) + z * exp(-0.5 * z * z) / sqrt(2.0 * PO_PI);
+}
+
+/* pre-activations z[l] and activations a[l] of one sample, l = 0..4 (a[0] = x) */
+static void po_mlp_sample(const double *w, const double *x, double a[5][PO_MLP_OUT],
+                          double z[5][PO_MLP_OUT]) {
+  for (int i = 0; i < PO_MLP_IN; ++i) a[0][i] = x[i];
+  const double *p = w;
+  for (int l = 0; l < 4; ++l) {
+    int ni = po_dims[l], no = po_dims[l + 1];
+    const double *W = p, *b = p + (long)no * ni;
+    for (int o = 0; o < no; ++o) {
+      double s = b[o];
+      for (int i = 0; i < ni; ++i) s += W[(long)o * ni + i] * a[l][i];
+      z[l + 1][o] = s;
+      a[l + 1][o] = (l < 3) ? po_gelu(s) : s;
+    }
+    p += (long)no * ni + no;
+  }
+}
+
+void po_mlp_forward(const double *w, const double *x, int n, double *yhat) {
+  double a[5][PO_MLP_OUT], z[5][PO_MLP_OUT];
+  for (int s = 0; s < n; ++s) {
+    po_mlp_sample(w, x + (long)s * PO_MLP_IN, a, z);
+    for (int o = 0; o < PO_MLP_OUT; ++o) yhat[(long)s * PO_MLP_OUT + o] = a[4][o];
+  }
+}
+
+double po_mlp_loss_grad(const double *w, const double *x, const double *y, int n, double *grad) {
+  long np = po_mlp_nparams();
+  for (long k = 0; k < np; ++k) grad[k] = 0.0;
+  long off[4];
+  off[0] = 0;
+  for (int l = 1; l < 4; ++l) off[l] = off[l - 1] + (long)po_dims[l] * po_dims[l - 1] + po_dims[l];
+  double loss = 0.0, a[5][PO_MLP_OUT], z[5][PO_MLP_OUT], d[PO_MLP_OUT], dn[PO_MLP_OUT];
+  const double scale = 1.0 / ((double)n * PO_MLP_OUT);
+  for (int s = 0; s < n; ++s) {
+    po_mlp_sample(w, x + (long)s * PO_MLP_IN, a, z);
+    for (int o = 0; o < PO_MLP_OUT; ++o) {
+      double r = a[4][o] - y[(long)s * PO_MLP_OUT + o];
+      loss += r * r;
+      d[o] = 2.0 * r * scale;  /* dL/dz of the linear output layer */
+    }
+    for (int l = 3; l >= 0; --l) {  /* layer l maps a[l] -> z[l+1] */
+      int ni = po_dims[l], no = po_dims[l + 1];
+      const double *W = w + off[l];
+      double *gW = grad + off[l], *gb = grad + off[l] + (long)no * ni;
+      for (int o = 0; o < no; ++o) {
+        gb[o] += d[o];
+        for (int i = 0; i < ni; ++i) gW[(long)o * ni + i] += d[o] * a[l][i];
+      }
+      if (l > 0) {
+        for (int i = 0; i < ni; ++i) {
+          double s2 = 0.0;
+          for (int o = 0; o < no; ++o) s2 += W[(long)o * ni + i] * d[o];
+          dn[i] = s2 * po_gelu_d(z[l][i]);
+        }
+        for (int i = 0; i < ni; ++i) d[i] = dn[i];
+      }
+    }
+  }
+  return loss * scale;
+}
+
+void po_mlp_adam(double *w, const double *g, double *m, double *v, long np, int t, double lr) {
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+  for (long k = 0; k < np; ++k) {
+    m[k] = b1 * m[k] + (1.0 - b1) * g[k];
+    v[k] = b2 * v[k] + (1.0 - b2) * g[k] * g[k];
+    w[k] -= lr * (m[k] / c1) / (sqrt(v[k] / c2) + eps);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Seeding: features, labels, seed tree.                                     */
+void po_seed_features(double t, double tp, double mu, double T, double Omega, double lx,
+                      double ly, int channel, double x[7], int cellmap[256]) {
+  /* reduce l to [-pi, pi)^2; an odd number of 2 pi shifts moves p by pi */
+  double nx = floor((lx + PO_PI) / (2.0 * PO_PI)), ny = floor((ly + PO_PI) / (2.0 * PO_PI));
+  double rx = lx - 2.0 * PO_PI * nx, ry = ly - 2.0 * PO_PI * ny;
+  int hx = ((long)nx) & 1, hy = ((long)ny) & 1;
+  /* D4 element taking (rx, ry) to the wedge: mirrors first, then the swap */
+  int mx = rx < 0.0, my = ry < 0.0;
+  double ax = fabs(rx), ay = fabs(ry);
+  int sw = ay > ax;
+  x[0] = (sw ? ay : ax) / PO_PI;
+  x[1] = (sw ? ax : ay) / PO_PI;
+  x[2] = mu / t;
+  x[3] = log10(T / t);
+  x[4] = tp / t;
+  x[5] = log10(Omega / t);
+  x[6] = (channel == PO_PH) ? 1.0 : -1.0;
+  /* cell map by geometry: the centre of container cell c, moved the same way */
+  const double w = 2.0 * PO_PI / PO_SEED_G;
+  for (int j = 0; j < PO_SEED_G; ++j)
+    for (int i = 0; i < PO_SEED_G; ++i) {
+      double px = -PO_PI + (i + 0.5) * w, py = -PO_PI + (j + 0.5) * w;
+      if (hx) px += PO_PI;
+      if (hy) py += PO_PI;
+      if (px >= PO_PI) px -= 2.0 * PO_PI;
+      if (py >= PO_PI) py -= 2.0 * PO_PI;
+      if (mx) px = -px;
+      if (my) py = -py;
+      if (sw) {
+        double tt = px;
+        px = py;
+        py = tt;
+      }
+      int ci = (int)floor((px + PO_PI) / w), cj = (int)floor((py + PO_PI) / w);
+      cellmap[j * PO_SEED_G + i] = cj * PO_SEED_G + ci;
+    }
+}
+
+/* area of [a0,a1) x [b0,b1) inside cell (i, j), as a fraction of the cell */
+static double po_cell_overlap(const double *r, int i, int j) {
+  const double w = 2.0 * PO_PI / PO_SEED_G;
+  double cx0 = -PO_PI + i * w, cy0 = -PO_PI + j * w;
+  double ox = fmin(r[1], cx0 + w) - fmax(r[0], cx0);
+  double oy = fmin(r[3], cy0 + w) - fmax(r[2], cy0);
+  if (ox <= 0.0 || oy <= 0.0) return 0.0;
+  /* quadtree rectangles cover dyadic fractions of a cell (multiples of
+     4^-20 down to depth 24): snap away the rounding of the coordinates */
+  return nearbyint((ox / w) * (oy / w) * 1099511627776.0) / 1099511627776.0;
+}
+
+void po_tree_labels(const double *rects, long n, double y[256]) {
+  double cnt[256];
+  for (int c = 0; c < 256; ++c) cnt[c] = 0.0;
+  const double cell_area = (2.0 * PO_PI / PO_SEED_G) * (2.0 * PO_PI / PO_SEED_G);
+  for (long k = 0; k < n; ++k) {
+    const double *r = &rects[4 * k];
+    double area = (r[1] - r[0]) * (r[3] - r[2]);
+    for (int j = 0; j < PO_SEED_G; ++j)
+      for (int i = 0; i < PO_SEED_G; ++i) {
+        double f = po_cell_overlap(r, i, j);
+        if (f > 0.0) cnt[j * PO_SEED_G + i] += f * cell_area / area;
+      }
+  }
+  for (int c = 0; c < 256; ++c) y[c] = log2(1.0 + cnt[c]);
+}
+
+static double po_node_count(const double count[256], const double *r) {
+  double s = 0.0;
+  for (int j = 0; j < PO_SEED_G; ++j)
+    for (int i = 0; i < PO_SEED_G; ++i) {
+      double f = po_cell_overlap(r, i, j);
+      if (f > 0.0) s += f * count[j * PO_SEED_G + i];
+    }
+  return s;
+}
+
+/* leaves under node r at depth d; appends them to rects while room is left */
+static long po_seed_rec(const double count[256], const double *r, int d, int D, double thresh,
+                        double *rects, long *nw, long limit) {
+  if (d < D && po_node_count(count, r) >= thresh) {
+    long n = 0;
+    for (int a = 0; a < 4; ++a) {
+      double cr[4];
+      po_split_geo(r, a, cr);
+      n += po_seed_rec(count, cr, d + 1, D, thresh, rects, nw, limit);
+    }
+    return n;
+  }
+  if (rects && *nw < limit) memcpy(&rects[4 * (*nw)], r, 4 * sizeof(double));
+  ++*nw;
+  return 1;
+}
+
+long po_seed_tree(const double count[256], int dmax, double thresh, long limit, double *rects,
+                  int *dmax_used) {
+  const double root[4] = {-PO_PI, PO_PI, -PO_PI, PO_PI};
+  for (int D = dmax; D >= 0; --D) {
+    long nw = 0;
+    long n = po_seed_rec(count, root, 0, D, thresh, NULL, &nw, 0);
+    if (n <= limit || D == 0) {
+      if (rects) {
+        nw = 0;
+        po_seed_rec(count, root, 0, D, thresh, rects, &nw, limit);
+      }
+      if (dmax_used) *dmax_used = D;
+      return n;
+    }
+  }
+  return -1;
 }

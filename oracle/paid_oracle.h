@@ -98,6 +98,56 @@ int po_integrate_batch(const po_problem *prs, int n, const po_options *opt,
 /* Periodic trapezoid on an L x L grid (brute force). value: [n_ff][n_ff] */
 int po_brute(const po_problem *pr, int L, double *value);
 
+/* ------------------------------------------------------------------------
+ * Subdivision-density model (the learned seeding of the initial partition):
+ * a multilayer perceptron 7 -> 128 -> 128 -> 128 -> 256 with GELU(z) =
+ * z Phi(z) on the hidden layers and a linear output layer.  Parameters are
+ * one array: W1[128][7], b1[128], W2[128][128], b2[128], W3[128][128], b3[128],
+ * W4[256][128], b4[256] (row-major, out x in).  Loss: mean over samples and
+ * outputs of (yhat - y)^2.  FP64, plain loops. */
+#define PO_MLP_IN 7
+#define PO_MLP_HID 128
+#define PO_MLP_OUT 256
+long po_mlp_nparams(void);
+/* yhat [n][256] */
+void po_mlp_forward(const double *w, const double *x, int n, double *yhat);
+/* loss and its gradient (same layout as w) */
+double po_mlp_loss_grad(const double *w, const double *x, const double *y, int n, double *grad);
+/* one Adam step (beta1 0.9, beta2 0.999, eps 1e-8); m, v: moments, t: step >= 1 */
+void po_mlp_adam(double *w, const double *g, double *m, double *v, long np, int t, double lr);
+
+/* ------------------------------------------------------------------------
+ * Seeding the initial partition from a predicted subdivision density.
+ * The density lives on a 16 x 16 grid of cells over [-pi,pi)^2; cell (i, j)
+ * covers x in [-pi + i pi/8, -pi + (i+1) pi/8) and likewise y, stored at
+ * index 16 j + i.  Labels of a tree: y_c = log2(1 + n_c), n_c = the number
+ * of leaves in cell c, a leaf larger than a cell counting with the fraction
+ * of its area inside the cell.
+ *
+ * Model frame: the integrand at transfer momentum l equals the integrand at
+ * l - 2 pi e_x shifted by pi e_x in p (both energies are periodic), and the
+ * lattice is symmetric under the point group D4; so the model sees l
+ * reduced to [-pi,pi)^2 and then to the wedge 0 <= l_y <= l_x, and the cell
+ * map takes each cell of the container to the matching model cell.
+ * Features: l_x/pi, l_y/pi (reduced), mu/t, log10(T/t), t'/t, log10(Omega/t),
+ * channel (-1 pp, +1 ph). */
+#define PO_SEED_G 16
+void po_seed_features(double t, double tp, double mu, double T, double Omega, double lx,
+                      double ly, int channel, double x[7], int cellmap[256]);
+/* labels of n leaf rectangles [n][4] = (x0, x1, y0, y1) */
+void po_tree_labels(const double *rects, long n, double y[256]);
+/* po_integrate, also returning the labels of the final tree (mode B only) */
+int po_integrate_labels(const po_problem *pr, const po_options *opt, double *value,
+                        double *err, po_stats *st, double labels[256]);
+/* Seed tree from per-cell predicted leaf counts (container frame): a node is
+ * split while its predicted count (the area-weighted sum over the cells it
+ * overlaps) is >= thresh and its depth is < D.  D starts at dmax and is
+ * lowered until the tree has at most `limit` leaves.  Writes the leaves to
+ * rects [n][4] when non-NULL (capacity `limit`), *dmax_used = D; returns the
+ * leaf count. */
+long po_seed_tree(const double count[256], int dmax, double thresh, long limit, double *rects,
+                  int *dmax_used);
+
 #ifdef __cplusplus
 }
 #endif
