@@ -101,6 +101,9 @@ typedef struct {
   void *stream;         /* hipStream_t to run on, or NULL for a private stream */
   int profile;          /* 1: time the region-evaluation launches with HIP
                            events on the context stream (paid_stats.eval_*) */
+  int seed_dmax;        /* learned seeding: deepest level of the seed tree (0..12) */
+  double seed_kappa;    /* learned seeding: a node is split while its predicted
+                           leaf count is >= 4 seed_kappa */
 } paid_config;
 
 /* one parameter row: dispersion, temperature and flow scale */
@@ -122,11 +125,13 @@ typedef struct {
   double eval_seconds;  /* profile: summed duration of the region-evaluation launches */
   long eval_launches;   /* profile: number of those launches */
   long eval_items;      /* parents evaluated (each gives 4 children) */
+  long seeded;          /* containers started from a seed tree */
+  double seed_seconds;  /* model features and inference inside this call */
 } paid_stats;
 
 /* Fill *cfg with defaults (device 0, N = 4, batch 8, batch_max 1024, global
  * error, FP64, separable projection, nu = 1e-3, max_regions = 2^18,
- * automatic pool). */
+ * automatic pool, seed_dmax 8, seed_kappa 2). */
 int paid_config_default(paid_config *cfg);
 
 /* Create a context on cfg->device.  *out receives the context (NULL on
@@ -169,6 +174,77 @@ int paid_kernel_eval(struct paid_ctx *ctx, const paid_params *p, unsigned channe
 int paid_children_eval(struct paid_ctx *ctx, const paid_params *p, const double *l,
                        unsigned channel, const double *ff, int n_ff, int ff_L,
                        const int *codes, int n, double *q2n, double *err);
+
+/* ------------------------------------------------------------------------
+ * Learned seeding of the initial partition (not in the paper; the adaptive
+ * scheme of Alg. 2 still decides termination and every further split).
+ *
+ * A perceptron 7 -> 128 -> 128 -> 128 -> 256 (GELU(z) = z Phi(z) on the
+ * hidden layers, linear output, FP32) maps the features of a container to
+ * the predicted log2(1 + n_c) for the 16 x 16 cells c of the zone, n_c the
+ * number of leaves of its converged tree in c (leaves larger than a cell
+ * count with the share of their area).  Parameters are one FP32 array:
+ * per layer W [out][in] row-major, then b [out].
+ *
+ * Model frame.  l is reduced to [-pi, pi)^2 (an odd number of 2 pi shifts
+ * moves the integrand by pi in p) and then to the wedge 0 <= l_y <= l_x by
+ * the square's symmetries; the cells move with it.  Features: l_x/pi, l_y/pi
+ * (reduced), mu/t, log10(T/t), t'/t, log10(Omega/t), -1 (pp) or +1 (ph).
+ * Cell c = 16 j + i covers x in [-pi + i pi/8, -pi + (i+1) pi/8), likewise y.
+ *
+ * Seed tree: from the predicted counts (n = max(0, 2^y - 1) per cell, summed
+ * over the cells a node covers, shared by area below a cell) a node is split
+ * while its count is >= 4 seed_kappa and its depth < D; D starts at
+ * seed_dmax and is lowered until the tree has at most max_regions/4 leaves.
+ * Only the leaves of the seed tree are integrated; the adaptive loop then
+ * continues from them.
+ */
+#define PAID_MLP_IN 7
+#define PAID_MLP_OUT 256
+
+/* Number of model parameters (67072). */
+long paid_mlp_nparams(void);
+
+/* Use the model `weights` ([paid_mlp_nparams()] FP32, copied) for the
+ * seeding of every later paid_integrate call on ctx; NULL turns seeding off. */
+int paid_set_seed_model(struct paid_ctx *ctx, const float *weights);
+
+/* Make every later paid_integrate call on ctx also write, per container in
+ * the order of `out`, its model features [n_ctr][7] and the labels of its
+ * converged tree in the model frame [n_ctr][256] (FP32).  Both pointers are
+ * caller-owned, sized for each call, host or device; NULLs turn it off. */
+int paid_set_label_output(struct paid_ctx *ctx, float *features, float *labels);
+
+/* Model forward pass: x [n][7] -> y [n][256]. */
+int paid_mlp_forward(struct paid_ctx *ctx, const float *w, const float *x, int n, float *y);
+
+/* Mean squared error over n samples and 256 outputs, and its gradient
+ * grad [nparams] (same layout as w); *loss may be NULL.  n <= 65536. */
+int paid_mlp_loss_grad(struct paid_ctx *ctx, const float *w, const float *x, const float *y,
+                       int n, float *grad, double *loss);
+
+/* One Adam step in place (beta1 0.9, beta2 0.999, eps 1e-8, step t >= 1):
+ * m, v are the moment arrays, all [nparams], device memory only. */
+int paid_mlp_adam(struct paid_ctx *ctx, float *w, const float *grad, float *m, float *v, int t,
+                  float lr);
+
+typedef struct {
+  int steps;              /* Adam steps */
+  int batch;              /* samples per step, 1..1024 */
+  float lr, lr_final;     /* learning rate, cosine decay from lr to lr_final */
+  unsigned long long seed;/* shuffling and initialisation */
+  int init;               /* 1: initialise w (normal, std 1/sqrt(fan-in)), 0: start from w */
+  int use_graph;          /* 1: capture one step in a HIP graph and replay it */
+} paid_train_opts;
+
+/* Defaults: 3000 steps, batch 256, lr 2e-3 -> 5e-5, seed 1, init 1, graph 1. */
+int paid_train_opts_default(paid_train_opts *o);
+
+/* Train the model on the GPU: minibatches drawn without replacement from
+ * n samples (x [n][7], y [n][256]), reshuffled every pass; w [nparams]
+ * in/out; loss_hist NULL or [steps] FP64 minibatch losses. */
+int paid_seed_train(struct paid_ctx *ctx, const float *x, const float *y, int n,
+                    const paid_train_opts *opts, float *w, double *loss_hist);
 
 /* Release the context and everything it owns.  NULL is accepted. */
 void paid_destroy(struct paid_ctx *ctx);

@@ -37,7 +37,8 @@ class Config(C.Structure):
                 ("err_mode", C.c_int), ("precision", C.c_int), ("gram", C.c_int),
                 ("kind", C.c_int), ("nu", C.c_double), ("max_regions", C.c_long),
                 ("max_active", C.c_int), ("pool_gib", C.c_double),
-                ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int)]
+                ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int),
+                ("seed_dmax", C.c_int), ("seed_kappa", C.c_double)]
 
 
 class Params(C.Structure):
@@ -50,14 +51,23 @@ class Stats(C.Structure):
                 ("splits", C.c_long), ("kernel_evals", C.c_long), ("rounds", C.c_long),
                 ("launch_rounds", C.c_long), ("max_depth", C.c_int), ("max_active", C.c_int),
                 ("seconds", C.c_double), ("eval_seconds", C.c_double), ("eval_launches", C.c_long),
-                ("eval_items", C.c_long)]
+                ("eval_items", C.c_long), ("seeded", C.c_long), ("seed_seconds", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TrainOpts(C.Structure):
+    _fields_ = [("steps", C.c_int), ("batch", C.c_int), ("lr", C.c_float), ("lr_final", C.c_float),
+                ("seed", C.c_ulonglong), ("init", C.c_int), ("use_graph", C.c_int)]
+
+
+MLP_IN, MLP_OUT = 7, 256
+
 EXPORTS = ("paid_config_default", "paid_create", "paid_integrate", "paid_kernel_eval",
-           "paid_children_eval", "paid_destroy", "paid_last_error")
+           "paid_children_eval", "paid_destroy", "paid_last_error", "paid_mlp_nparams",
+           "paid_set_seed_model", "paid_set_label_output", "paid_mlp_forward",
+           "paid_mlp_loss_grad", "paid_mlp_adam", "paid_train_opts_default", "paid_seed_train")
 
 _lib = None
 
@@ -69,6 +79,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run paid_1610_09991_amd/build.py "
                                "(or __graft_entry__.build()) first")
+        try:
+            # torch and libpaid name the same HIP runtime (libamdhip64.so.7);
+            # loading torch first makes the process hold one runtime, torch's,
+            # so that torch's device memory and streams are valid in libpaid
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
         L.paid_config_default.argtypes = [C.POINTER(Config)]
@@ -81,6 +98,15 @@ def lib():
         L.paid_destroy.argtypes = [vp]
         L.paid_last_error.argtypes = [vp]
         L.paid_last_error.restype = C.c_char_p
+        L.paid_mlp_nparams.argtypes = []
+        L.paid_mlp_nparams.restype = C.c_long
+        L.paid_set_seed_model.argtypes = [vp, vp]
+        L.paid_set_label_output.argtypes = [vp, vp, vp]
+        L.paid_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.paid_mlp_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int, vp, dp]
+        L.paid_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float]
+        L.paid_train_opts_default.argtypes = [C.POINTER(TrainOpts)]
+        L.paid_seed_train.argtypes = [vp, vp, vp, C.c_int, C.POINTER(TrainOpts), vp, vp]
         _lib = L
     return _lib
 
@@ -191,3 +217,64 @@ class Context:
                                              ff_L, _ptr(cd), n, _ptr(q2n), _ptr(er)),
                     allow_noconv=False)
         return q2n, er
+
+    # ------------------------------------------------------------ learned seeding
+    def set_seed_model(self, weights):
+        """Seed later integrate() calls from this model (None: root start)."""
+        if weights is None:
+            self._check(lib().paid_set_seed_model(self.h, None), allow_noconv=False)
+            self._seed_w = None
+            return
+        w = weights if hasattr(weights, "data_ptr") else np.ascontiguousarray(weights, np.float32)
+        self._check(lib().paid_set_seed_model(self.h, _ptr(w)), allow_noconv=False)
+        self._seed_w = w
+
+    def set_label_output(self, features=None, labels=None):
+        """Arm per-container features [n][7] and tree labels [n][256] (FP32
+        arrays or tensors the caller keeps alive) for later integrate() calls."""
+        self._lab = (features, labels)
+        self._check(lib().paid_set_label_output(
+            self.h, _ptr(features) if features is not None else None,
+            _ptr(labels) if labels is not None else None), allow_noconv=False)
+
+    def mlp_forward(self, w, x, y=None):
+        n = x.shape[0]
+        if y is None:
+            y = np.zeros((n, MLP_OUT), dtype=np.float32)
+        self._check(lib().paid_mlp_forward(self.h, _ptr(w), _ptr(x), n, _ptr(y)),
+                    allow_noconv=False)
+        return y
+
+    def mlp_loss_grad(self, w, x, y, grad=None):
+        n = x.shape[0]
+        if grad is None:
+            grad = np.zeros(mlp_nparams(), dtype=np.float32)
+        loss = C.c_double(0.0)
+        self._check(lib().paid_mlp_loss_grad(self.h, _ptr(w), _ptr(x), _ptr(y), n, _ptr(grad),
+                                             C.byref(loss)), allow_noconv=False)
+        return loss.value, grad
+
+    def mlp_adam(self, w, g, m, v, t, lr):
+        """one Adam step in place on device tensors w, m, v"""
+        self._check(lib().paid_mlp_adam(self.h, _ptr(w), _ptr(g), _ptr(m), _ptr(v), t, lr),
+                    allow_noconv=False)
+
+    def seed_train(self, x, y, w=None, **opts):
+        """Train the density model on the GPU; returns (w, minibatch losses)."""
+        o = TrainOpts()
+        lib().paid_train_opts_default(C.byref(o))
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown training option {k}")
+            setattr(o, k, v)
+        if w is None:
+            w = np.zeros(mlp_nparams(), dtype=np.float32)
+            o.init = 1
+        hist = np.zeros(o.steps)
+        self._check(lib().paid_seed_train(self.h, _ptr(x), _ptr(y), x.shape[0], C.byref(o), _ptr(w),
+                                          _ptr(hist)), allow_noconv=False)
+        return w, hist
+
+
+def mlp_nparams() -> int:
+    return lib().paid_mlp_nparams()

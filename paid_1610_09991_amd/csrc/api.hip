@@ -7,7 +7,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -52,6 +54,10 @@ struct paid_ctx {
   DevBuf entries, tab, zeta, svals, ctr, qv, ffc;
   DevBuf code, key, Q, E;
   DevBuf slot_i, slot_d, sel, dv, de, dep, itau, errp, stl, counters, outs, errs;
+  // learned seeding
+  DevBuf seedw, sfeat, sfold, sy, sact, pyr, seedd, ifill, labtmp;
+  bool seed_on = false;
+  float *feat_out = nullptr, *lab_out = nullptr;
   int *host_counters = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profile: around the evaluation launch
 };
@@ -237,6 +243,54 @@ int to_host(paid_ctx *c, const T *p, size_t n, std::vector<T> &out) {
   return PAID_OK;
 }
 
+// device view of a caller array: the pointer itself, or a staged copy in tmp
+template <class T>
+int stage_in(paid_ctx *c, const T *p, size_t n, DevBuf &tmp, const T *&d) {
+  if (is_device_ptr(p)) {
+    d = p;
+    return PAID_OK;
+  }
+  HIPCHK(c, tmp.ensure(sizeof(T) * (n ? n : 1)));
+  if (n) HIPCHK(c, hipMemcpyAsync(tmp.p, p, sizeof(T) * n, hipMemcpyHostToDevice, c->stream));
+  d = tmp.as<T>();
+  return PAID_OK;
+}
+
+// device buffer for a caller output: the pointer itself, or tmp (copied back
+// with finish_out)
+template <class T>
+int stage_out(paid_ctx *c, T *p, size_t n, DevBuf &tmp, T *&d) {
+  if (is_device_ptr(p)) {
+    d = p;
+    return PAID_OK;
+  }
+  HIPCHK(c, tmp.ensure(sizeof(T) * (n ? n : 1)));
+  d = tmp.as<T>();
+  return PAID_OK;
+}
+
+template <class T>
+int finish_out(paid_ctx *c, T *p, const T *d, size_t n) {
+  if (p != d && n) HIPCHK(c, hipMemcpyAsync(p, d, sizeof(T) * n, hipMemcpyDeviceToHost, c->stream));
+  return PAID_OK;
+}
+
+// the full set of per-sample training buffers for n samples, carved from buf
+int carve_act(paid_ctx *c, DevBuf &buf, int n, MlpAct &a, float *&yhat, float *&dY) {
+  const size_t h = (size_t)kMlpHid * n, o = (size_t)kMlpOut * n;
+  HIPCHK(c, buf.ensure(sizeof(float) * (9 * h + 2 * o)));
+  float *p = buf.as<float>();
+  for (int l = 0; l < 3; ++l) {
+    a.Z[l] = p + (size_t)l * h;
+    a.A[l] = p + (size_t)(3 + l) * h;
+    a.D[l] = p + (size_t)(6 + l) * h;
+  }
+  a.Z[3] = nullptr;
+  yhat = p + 9 * h;
+  dY = yhat + o;
+  return PAID_OK;
+}
+
 struct SlotLayout {  // carving of the small per-slot arrays
   int *cid, *state, *nleaf, *selcnt, *woff, *flags, *depth;
 };
@@ -262,6 +316,8 @@ int paid_config_default(paid_config *cfg) {
   cfg->pool_gib = 0.0;
   cfg->gauss[2] = 1.0;
   cfg->stream = nullptr;
+  cfg->seed_dmax = 8;
+  cfg->seed_kappa = 2.0;
   return PAID_OK;
 }
 
@@ -286,6 +342,8 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
   if (cfg.max_regions < 16 || cfg.max_regions > (1L << 28))
     return fail(nullptr, PAID_EINVAL, "max_regions must be in [16, 2^28]");
   if (!(cfg.nu >= 0)) return fail(nullptr, PAID_EINVAL, "nu must be >= 0");
+  if (cfg.seed_dmax < 0 || cfg.seed_dmax > 12) return fail(nullptr, PAID_EINVAL, "seed_dmax must be 0..12");
+  if (!(cfg.seed_kappa > 0)) return fail(nullptr, PAID_EINVAL, "seed_kappa must be > 0");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev == 0) return fail(nullptr, PAID_EDEVICE, "no HIP device");
@@ -332,7 +390,9 @@ void paid_destroy(paid_ctx *c) {
   DevBuf *bufs[] = {&c->entries, &c->tab,  &c->zeta,  &c->svals, &c->ctr,   &c->qv,
                     &c->ffc,     &c->code, &c->key,   &c->Q,     &c->E,     &c->slot_i,
                     &c->slot_d,  &c->sel,  &c->dv,    &c->de,    &c->dep,   &c->itau,
-                    &c->errp,    &c->stl,  &c->counters, &c->outs, &c->errs};
+                    &c->errp,    &c->stl,  &c->counters, &c->outs, &c->errs,
+                    &c->seedw,   &c->sfeat, &c->sfold, &c->sy,  &c->sact,  &c->pyr,
+                    &c->seedd,   &c->ifill, &c->labtmp};
   for (DevBuf *b : bufs) b->release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -418,7 +478,8 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   HIPCHK(c, c->dv.ensure(sizeof(double) * W * (size_t)bmax * MU));
   HIPCHK(c, c->de.ensure(sizeof(double) * W * (size_t)bmax));
   if (store_E) HIPCHK(c, c->dep.ensure(sizeof(double) * W * (size_t)bmax * MU));
-  HIPCHK(c, c->stl.ensure(sizeof(long) * 2 * W));
+  HIPCHK(c, c->stl.ensure(sizeof(long) * 3 * W));
+  HIPCHK(c, c->ifill.ensure(sizeof(int) * W * (size_t)bmax));
   HIPCHK(c, c->counters.ensure(256));
   const bool out_dev = is_device_ptr(out), err_dev = err_out && is_device_ptr(err_out);
   const size_t out_bytes = sizeof(double) * (size_t)n_ctr * M * M;
@@ -474,6 +535,8 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   P.dep = store_E ? c->dep.as<double>() : nullptr;
   P.st_rounds = c->stl.as<long>();
   P.st_splits = c->stl.as<long>() + W;
+  P.st_evals = c->stl.as<long>() + 2 * W;
+  P.ifill = c->ifill.as<int>();
   int *cnt = c->counters.as<int>();
   P.qhead = cnt;            // [0]
   P.counters = cnt + 4;     // [4..7]: done, not converged, work items
@@ -483,7 +546,52 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
 
   HIPCHK(c, hipMemsetAsync(c->slot_i.p, 0, sizeof(int) * (8 * W + 8), c->stream));
   HIPCHK(c, hipMemsetAsync(c->counters.p, 0, 256, c->stream));
-  HIPCHK(c, hipMemsetAsync(c->stl.p, 0, sizeof(long) * 2 * W, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->stl.p, 0, sizeof(long) * 3 * W, c->stream));
+
+  // learned seeding: model features of every container, then the model
+  const bool want_labels = c->lab_out != nullptr || c->feat_out != nullptr;
+  double seed_s = 0.0;
+  if (c->seed_on || want_labels) {
+    auto ts = std::chrono::steady_clock::now();
+    HIPCHK(c, c->sfeat.ensure(sizeof(float) * kMlpIn * (size_t)n_ctr));
+    HIPCHK(c, c->sfold.ensure(sizeof(int) * (size_t)n_ctr));
+    HIPCHK(c, launch_seed_features(c->entries.as<Entry>(), c->qv.as<double>(), n_ctr, n_q, n_ch,
+                                   ch_first, c->sfeat.as<float>(), c->sfold.as<int>(), c->stream));
+    P.seed_fold = c->sfold.as<int>();
+    if (c->seed_on) {
+      HIPCHK(c, c->sy.ensure(sizeof(float) * kMlpOut * (size_t)n_ctr));
+      const int chunk = n_ctr < 65536 ? n_ctr : 65536;
+      HIPCHK(c, c->sact.ensure(sizeof(float) * 2 * kMlpHid * (size_t)chunk));
+      MlpAct a;
+      memset(&a, 0, sizeof a);
+      a.A[0] = c->sact.as<float>();
+      a.A[1] = a.A[0] + (size_t)kMlpHid * chunk;
+      a.A[2] = a.A[0];
+      for (int o = 0; o < n_ctr; o += chunk) {
+        int nn = n_ctr - o < chunk ? n_ctr - o : chunk;
+        HIPCHK(c, mlp_forward(c->seedw.as<float>(), c->sfeat.as<float>() + (size_t)o * kMlpIn, nn, a,
+                              c->sy.as<float>() + (size_t)o * kMlpOut, c->stream));
+      }
+      HIPCHK(c, c->pyr.ensure(sizeof(double) * kPyr * (size_t)W));
+      HIPCHK(c, c->seedd.ensure(sizeof(int) * (size_t)W));
+      P.seed_y = c->sy.as<float>();
+      P.pyr = c->pyr.as<double>();
+      P.seed_d = c->seedd.as<int>();
+      P.seed_dmax = cfg.seed_dmax;
+      P.seed_thresh = 4.0 * cfg.seed_kappa;
+      P.seed_limit = cap / 4;
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (c->lab_out) {
+      if (is_device_ptr(c->lab_out)) {
+        P.labels = c->lab_out;
+      } else {
+        HIPCHK(c, c->labtmp.ensure(sizeof(float) * kMlpOut * (size_t)n_ctr));
+        P.labels = c->labtmp.as<float>();
+      }
+    }
+    seed_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+  }
 
   int dev_cus = 256;
   {
@@ -520,7 +628,13 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   if (!out_dev) HIPCHK(c, hipMemcpyAsync(out, c->outs.p, out_bytes, hipMemcpyDeviceToHost, c->stream));
   if (err_out && !err_dev)
     HIPCHK(c, hipMemcpyAsync(err_out, c->errs.p, out_bytes, hipMemcpyDeviceToHost, c->stream));
-  long long gs[4] = {0, 0, 0, 0};
+  if (c->feat_out)
+    HIPCHK(c, hipMemcpyAsync(c->feat_out, c->sfeat.p, sizeof(float) * kMlpIn * (size_t)n_ctr,
+                             hipMemcpyDefault, c->stream));
+  if (c->lab_out && P.labels != c->lab_out)
+    HIPCHK(c, hipMemcpyAsync(c->lab_out, P.labels, sizeof(float) * kMlpOut * (size_t)n_ctr,
+                             hipMemcpyDefault, c->stream));
+  long long gs[5] = {0, 0, 0, 0, 0};
   HIPCHK(c, hipMemcpyAsync(gs, P.gstats, sizeof gs, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const int notconv = c->host_counters[1];
@@ -532,13 +646,15 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
     stats->splits = gs[1];
     stats->regions = gs[2];
     stats->max_depth = (int)gs[3];
-    stats->kernel_evals = 81L * n_ctr + 289L * gs[1];
+    stats->kernel_evals = gs[4];
     stats->launch_rounds = rounds;
     stats->max_active = (int)W;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     stats->eval_seconds = eval_ms * 1e-3;
     stats->eval_launches = cfg.profile ? rounds : 0;
     stats->eval_items = eval_items;
+    stats->seeded = c->seed_on ? n_ctr : 0;
+    stats->seed_seconds = seed_s;
   }
   return notconv ? PAID_ENOCONV : PAID_OK;
 }
@@ -618,7 +734,7 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
                                    channel == PAID_PH ? 1 : 0, c->stream));
   const int M = n_ff, MU = M * (M + 1) / 2;
   const long cap = 4L * n;
-  DevBuf code, key, Q, si, dv, de, itau, cnt, ctrid;
+  DevBuf code, key, Q, si, dv, de, itau, cnt, ctrid, ifl;
   HIPCHK(c, code.ensure(sizeof(uint64_t) * cap));
   HIPCHK(c, key.ensure(sizeof(double) * cap));
   HIPCHK(c, Q.ensure(sizeof(double) * cap * MU));
@@ -627,6 +743,7 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
   HIPCHK(c, de.ensure(sizeof(double) * (size_t)n));
   HIPCHK(c, itau.ensure(sizeof(float) * MU));
   HIPCHK(c, cnt.ensure(256));
+  HIPCHK(c, ifl.ensure(sizeof(int) * (size_t)n));
   HIPCHK(c, hipMemsetAsync(Q.p, 0, sizeof(double) * cap * MU, c->stream));
   HIPCHK(c, hipMemsetAsync(key.p, 0, sizeof(double) * cap, c->stream));
   HIPCHK(c, hipMemcpyAsync(code.p, pc.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, c->stream));
@@ -685,6 +802,7 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
   P.dv = dv.as<double>();
   P.de = de.as<double>();
   P.counters = cnt.as<int>() + 4;
+  P.ifill = ifl.as<int>();
   HIPCHK(c, launch_eval(P, n < 4096 ? n : 4096, c->stream));
   std::vector<double> hQ((size_t)cap * MU), hk(cap);
   HIPCHK(c, hipMemcpyAsync(hQ.data(), Q.p, sizeof(double) * cap * MU, hipMemcpyDeviceToHost, c->stream));
@@ -699,6 +817,222 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
     }
   HIPCHK(c, hipMemcpy(q2n, oq.data(), sizeof(double) * oq.size(), hipMemcpyDefault));
   HIPCHK(c, hipMemcpy(err, oe.data(), sizeof(double) * oe.size(), hipMemcpyDefault));
+  return PAID_OK;
+}
+
+
+long paid_mlp_nparams(void) { return mlp_layout().total; }
+
+int paid_set_seed_model(paid_ctx *c, const float *w) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  if (!w) {
+    c->seed_on = false;
+    return PAID_OK;
+  }
+  const long np = mlp_layout().total;
+  HIPCHK(c, c->seedw.ensure(sizeof(float) * np));
+  HIPCHK(c, hipMemcpyAsync(c->seedw.p, w, sizeof(float) * np, hipMemcpyDefault, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<float> chk(np);
+  HIPCHK(c, hipMemcpy(chk.data(), c->seedw.p, sizeof(float) * np, hipMemcpyDeviceToHost));
+  for (long i = 0; i < np; ++i)
+    if (!std::isfinite(chk[i])) {
+      c->seed_on = false;
+      return fail(c, PAID_EINVAL, "model weight %ld is not finite", i);
+    }
+  c->seed_on = true;
+  return PAID_OK;
+}
+
+int paid_set_label_output(paid_ctx *c, float *features, float *labels) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  c->feat_out = features;
+  c->lab_out = labels;
+  return PAID_OK;
+}
+
+int paid_mlp_forward(paid_ctx *c, const float *w, const float *x, int n, float *y) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if (!w || !x || !y || n < 0) return fail(c, PAID_EINVAL, "bad arguments");
+  if (n == 0) return PAID_OK;
+  if (n > (1 << 24)) return fail(c, PAID_EINVAL, "n must be <= 2^24");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const long np = mlp_layout().total;
+  DevBuf tw, tx, ty, act;
+  const float *dw, *dx;
+  float *dy;
+  int rc;
+  if ((rc = stage_in(c, w, np, tw, dw)) != PAID_OK) return rc;
+  if ((rc = stage_in(c, x, (size_t)n * kMlpIn, tx, dx)) != PAID_OK) return rc;
+  if ((rc = stage_out(c, y, (size_t)n * kMlpOut, ty, dy)) != PAID_OK) return rc;
+  HIPCHK(c, act.ensure(sizeof(float) * 2 * kMlpHid * (size_t)n));
+  MlpAct a;
+  memset(&a, 0, sizeof a);
+  a.A[0] = act.as<float>();
+  a.A[1] = a.A[0] + (size_t)kMlpHid * n;
+  a.A[2] = a.A[0];
+  HIPCHK(c, mlp_forward(dw, dx, n, a, dy, c->stream));
+  if ((rc = finish_out(c, y, dy, (size_t)n * kMlpOut)) != PAID_OK) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PAID_OK;
+}
+
+int paid_mlp_loss_grad(paid_ctx *c, const float *w, const float *x, const float *y, int n,
+                       float *grad, double *loss) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if (!w || !x || !y || !grad || n < 1 || n > 65536) return fail(c, PAID_EINVAL, "bad arguments");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const long np = mlp_layout().total;
+  DevBuf tw, tx, ty, tg, act, tl;
+  const float *dw, *dx, *dyl;
+  float *dg;
+  int rc;
+  if ((rc = stage_in(c, w, np, tw, dw)) != PAID_OK) return rc;
+  if ((rc = stage_in(c, x, (size_t)n * kMlpIn, tx, dx)) != PAID_OK) return rc;
+  if ((rc = stage_in(c, y, (size_t)n * kMlpOut, ty, dyl)) != PAID_OK) return rc;
+  if ((rc = stage_out(c, grad, np, tg, dg)) != PAID_OK) return rc;
+  MlpAct a;
+  float *yhat, *dY;
+  if ((rc = carve_act(c, act, n, a, yhat, dY)) != PAID_OK) return rc;
+  HIPCHK(c, tl.ensure(sizeof(double)));
+  HIPCHK(c, mlp_forward(dw, dx, n, a, yhat, c->stream));
+  HIPCHK(c, mlp_mse(yhat, dyl, (long)n * kMlpOut, dY, tl.as<double>(), nullptr, c->stream));
+  HIPCHK(c, mlp_backward(dw, dx, n, a, dY, dg, c->stream));
+  if ((rc = finish_out(c, grad, dg, np)) != PAID_OK) return rc;
+  double hl = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&hl, tl.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = hl;
+  return PAID_OK;
+}
+
+int paid_mlp_adam(paid_ctx *c, float *w, const float *g, float *m, float *v, int t, float lr) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if (!w || !g || !m || !v || t < 1 || !(lr > 0)) return fail(c, PAID_EINVAL, "bad arguments");
+  if (!is_device_ptr(w) || !is_device_ptr(g) || !is_device_ptr(m) || !is_device_ptr(v))
+    return fail(c, PAID_EINVAL, "paid_mlp_adam needs device arrays");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  HIPCHK(c, mlp_adam(w, g, m, v, mlp_layout().total, t, nullptr, lr, lr, 0, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PAID_OK;
+}
+
+int paid_train_opts_default(paid_train_opts *o) {
+  if (!o) return PAID_EINVAL;
+  memset(o, 0, sizeof *o);
+  o->steps = 3000;
+  o->batch = 256;
+  o->lr = 2e-3f;
+  o->lr_final = 5e-5f;
+  o->seed = 1;
+  o->init = 1;
+  o->use_graph = 1;
+  return PAID_OK;
+}
+
+int paid_seed_train(paid_ctx *c, const float *x, const float *y, int n, const paid_train_opts *oin,
+                    float *w, double *loss_hist) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  paid_train_opts o;
+  if (oin) o = *oin; else paid_train_opts_default(&o);
+  if (!x || !y || !w || n < 1) return fail(c, PAID_EINVAL, "bad arguments");
+  if (o.steps < 1 || o.batch < 1 || o.batch > 1024 || !(o.lr > 0) || !(o.lr_final >= 0))
+    return fail(c, PAID_EINVAL, "bad training options");
+  if ((long)o.steps * o.batch > (1L << 30)) return fail(c, PAID_EINVAL, "steps * batch too large");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const MlpLayout L = mlp_layout();
+  const long np = L.total;
+  const int bs = o.batch;
+  DevBuf tx, ty, wd, mv, idx, ctr, hist, xb, act, gr;
+  const float *dx, *dy;
+  int rc;
+  if ((rc = stage_in(c, x, (size_t)n * kMlpIn, tx, dx)) != PAID_OK) return rc;
+  if ((rc = stage_in(c, y, (size_t)n * kMlpOut, ty, dy)) != PAID_OK) return rc;
+  HIPCHK(c, wd.ensure(sizeof(float) * np));
+  if (o.init) {
+    std::mt19937_64 gen(o.seed ^ 0x5eed5eedULL);
+    std::vector<float> hw(np, 0.0f);
+    for (int l = 0; l < 4; ++l) {
+      std::normal_distribution<double> nd(0.0, 1.0 / sqrt((double)L.ni[l]));
+      for (long k = 0; k < (long)L.no[l] * L.ni[l]; ++k) hw[L.w[l] + k] = (float)nd(gen);
+    }
+    HIPCHK(c, hipMemcpyAsync(wd.p, hw.data(), sizeof(float) * np, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    HIPCHK(c, hipMemcpyAsync(wd.p, w, sizeof(float) * np, hipMemcpyDefault, c->stream));
+  }
+  HIPCHK(c, mv.ensure(sizeof(float) * 2 * np));
+  HIPCHK(c, hipMemsetAsync(mv.p, 0, sizeof(float) * 2 * np, c->stream));
+  // minibatch indices: consecutive passes over shuffled orders of the samples
+  {
+    std::mt19937_64 gen(o.seed);
+    std::vector<int> perm(n), hidx((size_t)o.steps * bs);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    size_t k = 0;
+    while (k < hidx.size()) {
+      for (int i = n - 1; i > 0; --i) {
+        std::uniform_int_distribution<int> ud(0, i);
+        std::swap(perm[i], perm[ud(gen)]);
+      }
+      for (int i = 0; i < n && k < hidx.size(); ++i) hidx[k++] = perm[i];
+    }
+    HIPCHK(c, idx.ensure(sizeof(int) * hidx.size()));
+    HIPCHK(c, hipMemcpyAsync(idx.p, hidx.data(), sizeof(int) * hidx.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  HIPCHK(c, ctr.ensure(sizeof(int)));
+  HIPCHK(c, hipMemsetAsync(ctr.p, 0, sizeof(int), c->stream));
+  HIPCHK(c, hist.ensure(sizeof(double) * o.steps));
+  HIPCHK(c, xb.ensure(sizeof(float) * (size_t)bs * (kMlpIn + kMlpOut)));
+  HIPCHK(c, gr.ensure(sizeof(float) * np));
+  MlpAct a;
+  float *yhat, *dY;
+  if ((rc = carve_act(c, act, bs, a, yhat, dY)) != PAID_OK) return rc;
+  float *Xb = xb.as<float>(), *Yb = Xb + (size_t)bs * kMlpIn;
+  float *W = wd.as<float>(), *M = mv.as<float>(), *V = M + np, *G = gr.as<float>();
+  int *step = ctr.as<int>();
+  double *lh = hist.as<double>();
+  auto one_step = [&](hipStream_t st) -> hipError_t {
+    hipError_t e;
+    if ((e = mlp_gather(dx, dy, idx.as<int>(), step, bs, Xb, Yb, st)) != hipSuccess) return e;
+    if ((e = mlp_forward(W, Xb, bs, a, yhat, st)) != hipSuccess) return e;
+    if ((e = mlp_mse(yhat, Yb, (long)bs * kMlpOut, dY, lh, step, st)) != hipSuccess) return e;
+    if ((e = mlp_backward(W, Xb, bs, a, dY, G, st)) != hipSuccess) return e;
+    if ((e = mlp_adam(W, G, M, V, np, 0, step, o.lr, o.lr_final, o.steps, st)) != hipSuccess) return e;
+    return mlp_count(step, st);
+  };
+  if (o.use_graph) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    hipError_t e = one_step(c->stream);
+    hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      HIPCHK(c, e != hipSuccess ? e : e2);
+    }
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(c, e);
+    for (int t = 0; t < o.steps && e == hipSuccess; ++t) e = hipGraphLaunch(ge, c->stream);
+    hipError_t e3 = hipStreamSynchronize(c->stream);
+    (void)hipGraphExecDestroy(ge);
+    HIPCHK(c, e);
+    HIPCHK(c, e3);
+  } else {
+    for (int t = 0; t < o.steps; ++t) HIPCHK(c, one_step(c->stream));
+  }
+  HIPCHK(c, hipMemcpyAsync(w, W, sizeof(float) * np, hipMemcpyDefault, c->stream));
+  if (loss_hist)
+    HIPCHK(c, hipMemcpyAsync(loss_hist, lh, sizeof(double) * o.steps, hipMemcpyDefault, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return PAID_OK;
 }
 

@@ -77,7 +77,56 @@ struct Problem {      // everything the round kernels need, passed by value
   long long *gstats;          // [0] rounds [1] splits [2] leaves [3] max depth
   // outputs (device)
   double *out, *err_out;      // [n_ctr][M][M]
+  // learned seeding (seed_y == NULL: every container starts from the root)
+  const float *seed_y;        // [n_ctr][256] predicted log2(1 + leaves) per model cell
+  const int *seed_fold;       // [n_ctr] container -> model frame (bits: hx hy mx my swap)
+  double *pyr;                // [W][kPyr] predicted leaf counts, levels 0..4
+  int *seed_d;                // [W] depth bound of the seed tree
+  int seed_dmax;
+  double seed_thresh;         // split while the predicted count >= this
+  long seed_limit;            // most leaves a seed tree may have
+  long *st_evals;             // [W] integrand evaluations
+  int *ifill;                 // [W*bmax] 1 if the work item evaluated its node grid
+  // tree labels of finished containers (model frame), NULL = off
+  float *labels;              // [n_ctr][256]
 };
+
+constexpr int kSeedG = 16;                    // cells per axis of the density grid
+constexpr int kPyr = 1 + 4 + 16 + 64 + 256;   // pyramid levels 0..4
+constexpr int kFlagSeed = 4;                  // slot flag: seed phase
+
+// model cell read by container cell (i, j) (x index i, y index j)
+__host__ __device__ inline int seed_model_cell(int fold, int i, int j) {
+  if (fold & 1) i = (i + kSeedG / 2) & (kSeedG - 1);
+  if (fold & 2) j = (j + kSeedG / 2) & (kSeedG - 1);
+  if (fold & 4) i = kSeedG - 1 - i;
+  if (fold & 8) j = kSeedG - 1 - j;
+  if (fold & 16) {
+    int t = i;
+    i = j;
+    j = t;
+  }
+  return j * kSeedG + i;
+}
+
+// level offset of depth d in the pyramid
+__host__ __device__ inline int pyr_off(int d) { return ((1 << (2 * d)) - 1) / 3; }
+
+// predicted leaf count of the quadtree node `code` of slot s
+__device__ inline double seed_count(const Problem &P, int s, uint64_t code) {
+  const int d = code_depth(code);
+  const double *py = P.pyr + (long)s * kPyr;
+  const int ix = (int)code_ix(code), iy = (int)code_iy(code);
+  if (d <= 4) return py[pyr_off(d) + (iy << d) + ix];
+  const int sh = d - 4;
+  return ldexp(py[pyr_off(4) + ((iy >> sh) << 4) + (ix >> sh)], -2 * sh);
+}
+
+// does the seed tree split this node?  (only while the slot is seeding)
+__device__ inline bool seed_split(const Problem &P, int s, uint64_t code) {
+  return (P.flags[s] & kFlagSeed) && code_depth(code) < P.seed_d[s] &&
+         seed_count(P, s, code) >= P.seed_thresh;
+}
 
 hipError_t launch_admit(const Problem &p, hipStream_t s);
 hipError_t launch_root(const Problem &p, hipStream_t s);
@@ -92,5 +141,31 @@ hipError_t launch_kernel_eval(const Entry *e, const double *tab, int ch, const d
                               const double *b, int n, double *out, hipStream_t s);
 
 hipError_t set_rule_constants(const RuleConst &rc);
+
+// ------------------------------------------------------------------ density model
+constexpr int kMlpIn = 7, kMlpHid = 128, kMlpOut = 256;
+struct MlpLayout {
+  int ni[4], no[4];
+  long w[4], b[4];   // offsets of W_l [out][in] and b_l [out]
+  long total;
+};
+struct MlpAct {        // per-sample buffers: Z pre-activations, A activations, D deltas
+  float *Z[4];         // Z[0..2] [n][128] (Z[3] unused)
+  float *A[3];         // [n][128]
+  float *D[3];         // [n][128]
+};
+MlpLayout mlp_layout();
+hipError_t launch_seed_features(const Entry *entries, const double *q, int n_ctr, int n_q, int n_ch,
+                                int ch_first, float *X, int *fold, hipStream_t s);
+hipError_t mlp_forward(const float *w, const float *x, int n, MlpAct &a, float *y, hipStream_t s);
+hipError_t mlp_backward(const float *w, const float *x, int n, MlpAct &a, float *dY, float *grad,
+                        hipStream_t s);
+hipError_t mlp_mse(const float *yhat, const float *y, long ne, float *dY, double *loss,
+                   const int *step, hipStream_t s);
+hipError_t mlp_adam(float *w, const float *g, float *m, float *v, long np, int t, const int *tdev,
+                    float lr0, float lr1, int steps, hipStream_t s);
+hipError_t mlp_gather(const float *X, const float *Y, const int *idx, const int *step, int bs,
+                      float *Xb, float *Yb, hipStream_t s);
+hipError_t mlp_count(int *c, hipStream_t s);
 
 }  // namespace paid

@@ -194,6 +194,32 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     if (t == 0) P.selcnt[s] = 0;
     return;
   }
+  if (P.flags[s] & kFlagSeed) {
+    // seed phase: the leaves the seed tree splits, in index order; no
+    // termination test while placeholders may exist.  The seed tree has at
+    // most cap/4 leaves, so the capacity is never reached here.
+    const long n = P.nleaf[s], base = (long)s * P.cap;
+    long kl = (P.cap - n) / 3;
+    if (kl > P.bmax) kl = P.bmax;
+    if (kl > n) kl = n;
+    const int kmax = (int)kl;
+    int *sel = P.sel + (long)s * P.bmax;
+    int out = 0;
+    for (long b0 = 0; b0 < n && out < kmax; b0 += blockDim.x) {
+      long i = b0 + t;
+      int flag = (i < n) && seed_split(P, s, P.code[base + i]), ex;
+      int tot = block_scan(flag, shi, ex);
+      if (flag && out + ex < kmax) sel[out + ex] = (int)i;
+      out += tot;
+    }
+    if (out > 0) {
+      if (t == 0) P.selcnt[s] = out < kmax ? out : kmax;
+      return;
+    }
+    __syncthreads();
+    if (t == 0) P.flags[s] &= ~kFlagSeed;
+    __syncthreads();
+  }
   double eps, deficit;
   int conv = tolerance_test(P, s, shd, eps, deficit);
   if (conv) {  // accept only on error sums recomputed from the leaves
@@ -389,15 +415,47 @@ __global__ void __launch_bounds__(kSelThreads) k_update(Problem P) {
     P.val[(long)s * P.MU + pid] += colv[pid];
     if (P.errp) P.errp[(long)s * P.MU + pid] += colp[pid];
   }
-  double de = 0.0;
-  for (int r = t; r < k; r += blockDim.x) de += P.de[it0 + r];
+  double de = 0.0, nf = 0.0;
+  for (int r = t; r < k; r += blockDim.x) {
+    de += P.de[it0 + r];
+    nf += (double)P.ifill[it0 + r];
+  }
   double d = block_sum(de, shd);
+  double fills = block_sum(nf, shd);
   if (t == 0) {
     P.err[s] += d;
+    P.st_evals[s] += (long)fills * (kNX * kNX);
     P.nleaf[s] += 3 * k;
     P.st_rounds[s] += 1;
     P.st_splits[s] += k;
   }
+}
+
+// Labels of a finished tree: per cell of the 16 x 16 grid, log2(1 + n) with
+// n the number of leaves in the cell (a leaf larger than a cell counts with
+// the share of its area inside), written at the model cell of the container.
+// All shares are powers of 1/4, so the LDS sums are exact in any order.
+__device__ void tree_labels(const Problem &P, int s, long c, double *cnt) {
+  const int t = threadIdx.x;
+  for (int k = t; k < kSeedG * kSeedG; k += blockDim.x) cnt[k] = 0.0;
+  __syncthreads();
+  const long n = P.nleaf[s], base = (long)s * P.cap;
+  for (long i = t; i < n; i += blockDim.x) {
+    const uint64_t code = P.code[base + i];
+    const int d = code_depth(code), ix = (int)code_ix(code), iy = (int)code_iy(code);
+    if (d >= 4) {
+      atomicAdd(&cnt[((iy >> (d - 4)) << 4) + (ix >> (d - 4))], 1.0);
+    } else {
+      const int span = 1 << (4 - d);
+      const double f = ldexp(1.0, -2 * (4 - d));
+      for (int b = 0; b < span; ++b)
+        for (int a = 0; a < span; ++a) atomicAdd(&cnt[((iy * span + b) << 4) + ix * span + a], f);
+    }
+  }
+  __syncthreads();
+  const int fold = P.seed_fold[c];
+  for (int k = t; k < kSeedG * kSeedG; k += blockDim.x)
+    P.labels[c * (kSeedG * kSeedG) + seed_model_cell(fold, k & 15, k >> 4)] = (float)log2(1.0 + cnt[k]);
 }
 
 __global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
@@ -406,6 +464,7 @@ __global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
   if (s >= P.W || P.state[s] != SLOT_DONE) return;
   if (P.flags[s] & 2) resum_errors(P, s, shd);  // budget exit: error sums from the leaves
   const long c = P.cid[s];
+  if (P.labels) tree_labels(P, s, c, shd);
   const int M = P.M;
   for (int pid = t; pid < P.MU; pid += blockDim.x) {
     int p = 0, k = pid;
@@ -428,6 +487,7 @@ __global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
     atomicAdd((unsigned long long *)&P.gstats[1], (unsigned long long)P.st_splits[s]);
     atomicAdd((unsigned long long *)&P.gstats[2], (unsigned long long)P.nleaf[s]);
     atomicMax((unsigned long long *)&P.gstats[3], (unsigned long long)P.st_depth[s]);
+    atomicAdd((unsigned long long *)&P.gstats[4], (unsigned long long)P.st_evals[s]);
     P.state[s] = SLOT_EMPTY;
   }
 }

@@ -511,36 +511,132 @@ __device__ void build_pidmap(int *map, int tid, int nthr) {
 }
 
 // ---------------------------------------------------------------- root
+// A region that the seed tree splits is stored as a placeholder: zero value,
+// error and key.  It is split in a later round of the seed phase before any
+// termination test runs, so the running sums never miss it.
+template <int L>
+__device__ void store_zero(const Problem &P, int s, long ri, uint64_t code) {
+  const int lane = lane_id();
+  const long base = (long)s * P.cap + ri;
+  for (int pid = lane; pid < P.MU; pid += 64) {
+    P.Q[base * P.MU + pid] = 0.0;
+    if (P.E) P.E[base * P.MU + pid] = 0.0f;
+  }
+  if (lane == 0) {
+    P.key[base] = 0.0;
+    P.code[base] = code;
+  }
+}
+
+// Seed admission (one wave): pyramid of predicted leaf counts in the
+// container's frame, n = max(0, 2^y - 1) per cell and 2 x 2 sums upwards,
+// and the depth bound D, lowered from seed_dmax until the seed tree has at
+// most seed_limit leaves.  Returns D.
+__device__ int seed_admit(const Problem &P, int s, int c, double *spyr) {
+  const int t = threadIdx.x;
+  const float *y = P.seed_y + (long)c * (kSeedG * kSeedG);
+  const int fold = P.seed_fold[c];
+  for (int cell = t; cell < kSeedG * kSeedG; cell += 64) {
+    double n = exp2((double)y[seed_model_cell(fold, cell & 15, cell >> 4)]) - 1.0;
+    spyr[pyr_off(4) + cell] = n > 0.0 ? n : 0.0;
+  }
+  __syncthreads();
+  for (int d = 3; d >= 0; --d) {
+    const int w = 1 << d, o = pyr_off(d), o1 = pyr_off(d + 1);
+    for (int k = t; k < w * w; k += 64) {
+      int i = k % w, j = k / w;
+      const double *ch = spyr + o1;
+      const int w1 = 2 * w;
+      spyr[o + k] = ((ch[(2 * j) * w1 + 2 * i] + ch[(2 * j) * w1 + 2 * i + 1]) +
+                     ch[(2 * j + 1) * w1 + 2 * i]) + ch[(2 * j + 1) * w1 + 2 * i + 1];
+    }
+    __syncthreads();
+  }
+  double *py = P.pyr + (long)s * kPyr;
+  for (int k = t; k < kPyr; k += 64) py[k] = spyr[k];
+  const double th = P.seed_thresh;
+  int D = P.seed_dmax;
+  for (; D > 0; --D) {
+    long long leaves = 0;
+    for (int k = t; k < kPyr; k += 64) {
+      int d = 0;
+      while (k >= pyr_off(d + 1)) ++d;
+      if (d > D) continue;
+      const int w = 1 << d, i = (k - pyr_off(d)) % w, j = (k - pyr_off(d)) / w;
+      bool exists = true;
+      for (int a = 0; a < d; ++a) {
+        int sh = d - a;
+        double ca = spyr[pyr_off(a) + ((j >> sh) << a) + (i >> sh)];
+        exists = exists && (a < D) && (ca >= th);
+      }
+      if (!exists) continue;
+      const double cn = spyr[k];
+      if (d < 4) {
+        if (!(d < D && cn >= th)) leaves += 1;
+      } else {  // uniform subtree below a cell: levels split while the share >= th
+        int lev = 0;
+        double v = cn;
+        while (4 + lev < D && v >= th) {
+          ++lev;
+          v *= 0.25;
+        }
+        leaves += 1LL << (2 * lev);
+      }
+    }
+    for (int off = 32; off >= 1; off >>= 1) leaves += __shfl_xor(leaves, off, 64);
+    if (leaves <= P.seed_limit) break;
+  }
+  return D;
+}
+
 template <int L, int GRAM>
 __global__ void __launch_bounds__(64) k_root(Problem P) {
   extern __shared__ double lds_raw[];
   __shared__ int pidmap[Dims<L>::MU];
+  __shared__ double spyr[kPyr];
   WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw);
   const int s = blockIdx.x;
   if (s >= P.W || P.state[s] != SLOT_NEW) return;
   build_pidmap<L>(pidmap, threadIdx.x, 64);
   const int c = P.cid[s];
-  const Ctr C = P.ctr[c];
-  const Entry E = P.entries[C.entry];
-  const double *tab = P.tab + E.tab_off;
   // key weights for the per-integral mode start at one
   for (int pid = threadIdx.x; pid < P.MU; pid += 64) P.itau[(long)s * P.MU + pid] = 1.0f;
   __syncthreads();
-  fill_nodes<L>(S, P, C, E, tab, kNF, -kPi, -kPi, kTwoPi);
-  if (GRAM == kSep) sep_stage1<L>(S, kNF, 1);
-  eval_rect<L, GRAM>(S, P, pidmap, kNF, 0, 0, kPi * kPi / (4.0 * kPi * kPi));
-  double key = store_region<L>(S, P, s, 0, make_code(0, 0, 0));
-  for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
-    P.val[(long)s * P.MU + pid] = S.cq[pid];
-    if (P.errp) P.errp[(long)s * P.MU + pid] = (double)(float)fabs(S.ce[pid]);
+  int D = 0;
+  bool placeholder = false;
+  if (P.seed_y) {
+    D = seed_admit(P, s, c, spyr);
+    placeholder = D > 0 && spyr[0] >= P.seed_thresh;
+  }
+  double key = 0.0;
+  if (placeholder) {
+    store_zero<L>(P, s, 0, make_code(0, 0, 0));
+    for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
+      P.val[(long)s * P.MU + pid] = 0.0;
+      if (P.errp) P.errp[(long)s * P.MU + pid] = 0.0;
+    }
+  } else {
+    const Ctr C = P.ctr[c];
+    const Entry E = P.entries[C.entry];
+    const double *tab = P.tab + E.tab_off;
+    fill_nodes<L>(S, P, C, E, tab, kNF, -kPi, -kPi, kTwoPi);
+    if (GRAM == kSep) sep_stage1<L>(S, kNF, 1);
+    eval_rect<L, GRAM>(S, P, pidmap, kNF, 0, 0, kPi * kPi / (4.0 * kPi * kPi));
+    key = store_region<L>(S, P, s, 0, make_code(0, 0, 0));
+    for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
+      P.val[(long)s * P.MU + pid] = S.cq[pid];
+      if (P.errp) P.errp[(long)s * P.MU + pid] = (double)(float)fabs(S.ce[pid]);
+    }
   }
   if (threadIdx.x == 0) {
     P.err[s] = key;
     P.nleaf[s] = 1;
     P.st_rounds[s] = 0;
     P.st_splits[s] = 0;
+    P.st_evals[s] = placeholder ? 0 : kNF * kNF;
     P.st_depth[s] = 0;
-    P.flags[s] = 0;
+    P.flags[s] = P.seed_y ? kFlagSeed : 0;
+    if (P.seed_y) P.seed_d[s] = D;
     P.state[s] = SLOT_ACTIVE;
   }
 }
@@ -581,18 +677,33 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int 
   }
   const int d = code_depth(pc);
   const uint64_t ix = code_ix(pc), iy = code_iy(pc);
+  // children that the seed tree splits again become placeholders (uniform
+  // in the wave); a parent with four of them needs no integrand values
+  int skip = 0;
+  if (P.seed_y && (P.flags[s] & kFlagSeed)) {
+    for (int ch = 0; ch < 4; ++ch)
+      if (seed_split(P, s, make_code(d + 1, 2 * ix + (ch & 1), 2 * iy + (ch >> 1)))) skip |= 1 << ch;
+  }
   const double wdt = kTwoPi * ldexp(1.0, -d);
   const double x0 = -kPi + (double)ix * wdt, y0 = -kPi + (double)iy * wdt;
-  fill_nodes<L>(S, P, C, E, tab, kNX, x0, y0, wdt);
-  if (GRAM == kSep) sep_stage1<L>(S, kNX, 2);
+  if (skip != 15) {
+    fill_nodes<L>(S, P, C, E, tab, kNX, x0, y0, wdt);
+    if (GRAM == kSep) sep_stage1<L>(S, kNX, 2);
+  }
   const double fa = (0.25 * wdt) * (0.25 * wdt) / (4.0 * kPi * kPi);
   double dkey = -pkey;
 #pragma unroll 1
   for (int ch = 0; ch < 4; ++ch) {
     int cx = ch & 1, cy = ch >> 1;
-    eval_rect<L, GRAM>(S, P, pidmap, kNX, cx, cy, fa);
     long ri = (ch == 0) ? leaf : nold + 3L * r + (ch - 1);
-    dkey += store_region<L>(S, P, s, ri, make_code(d + 1, 2 * ix + cx, 2 * iy + cy));
+    const uint64_t cc = make_code(d + 1, 2 * ix + cx, 2 * iy + cy);
+    if ((skip >> ch) & 1) {
+      store_zero<L>(P, s, ri, cc);
+      wave_sync();
+      continue;
+    }
+    eval_rect<L, GRAM>(S, P, pidmap, kNX, cx, cy, fa);
+    dkey += store_region<L>(S, P, s, ri, cc);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       int pid = lane + 64 * k;
@@ -616,6 +727,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int 
   }
   if (lane == 0) {
     P.de[it] = dkey;
+    if (P.ifill) P.ifill[it] = skip != 15;
     if (d + 1 > P.st_depth[s]) atomicMax(&P.st_depth[s], d + 1);
   }
 }
