@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--gram", choices=["separable", "mfma"], default="separable")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="arithmetic of the matrix-core projection (with --gram mfma)")
+    ap.add_argument("--seed-model", default=None,
+                    help="model file of the learned seeding (default: the shipped one)")
+    ap.add_argument("--no-seed", action="store_true", help="time the plain batched scheme only")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (the reference "
                          "for scaling the HBM byte counters) and exit")
@@ -130,20 +133,52 @@ def main():
     out = torch.empty((len(params), len(q), nch, M, M), dtype=torch.float64, device=dev)
     run = lambda o: ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=o)
 
-    for i in range(args.warmup):
-        _, _, st, rc = run(out)
-        print(f"# warmup {i}: {st['seconds']:.3f} s, regions {st['regions']}, rc {rc}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = []
-    for i in range(args.steps):
-        _, _, st, rc = run(out)
-        stats.append(st)
-        print(f"# step {i}: {st['seconds']:.3f} s, regions {st['regions']}, rc {rc}",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    # learned seeding: the shipped model (trained on the library's own trees,
+    # see paid_1610_09991_amd/seed_model.py) with its tuned threshold
+    from paid_1610_09991_amd import seed_model as SM
+    model = None
+    mpath = args.seed_model or SM.DEFAULT_MODEL
+    if not args.no_seed and os.path.exists(mpath):
+        w_seed, meta = SM.load(mpath)
+        model = {"file": os.path.relpath(mpath, ROOT), "kappa": meta["kappa"],
+                 "trees": meta["trees"], "train_seconds": meta["train_seconds"],
+                 "mse_held_out": meta["mse_held_out"]}
+
+    def timed(seeded, tag):
+        if seeded:
+            ctx.set_seed_model(w_seed, kappa=model["kappa"])
+        else:
+            ctx.set_seed_model(None)
+        for i in range(args.warmup):
+            _, _, st, rc = run(out)
+            print(f"# {tag} warmup {i}: {st['seconds']:.3f} s, regions {st['regions']}, "
+                  f"evals {st['kernel_evals']:.4g}, rc {rc}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = []
+        for i in range(args.steps):
+            _, _, st, rc = run(out)
+            sts.append(st)
+            print(f"# {tag} step {i}: {st['seconds']:.3f} s, regions {st['regions']}, "
+                  f"evals {st['kernel_evals']:.4g}, rc {rc}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, sts
+
+    variants = {}
+    dt_plain, st_plain = timed(False, "batched")
+    variants["batched"] = {"value": n_int * args.steps / dt_plain,
+                           "ms_per_step": 1e3 * dt_plain / args.steps,
+                           "kernel_evals": st_plain[-1]["kernel_evals"],
+                           "regions": st_plain[-1]["regions"]}
+    head, dt, stats = "batched", dt_plain, st_plain
+    if model is not None:
+        dt_seed, st_seed = timed(True, "batched+learned")
+        variants["batched_learned"] = {"value": n_int * args.steps / dt_seed,
+                                       "ms_per_step": 1e3 * dt_seed / args.steps,
+                                       "kernel_evals": st_seed[-1]["kernel_evals"],
+                                       "regions": st_seed[-1]["regions"],
+                                       "seed_seconds": st_seed[-1]["seed_seconds"]}
+        head, dt, stats = "batched_learned", dt_seed, st_seed
     ms = 1e3 * dt / args.steps
     value = n_int * args.steps / dt
 
@@ -168,19 +203,24 @@ def main():
             "dtype": "f64" if args.precision == "fp64" else f"{args.precision} projection, f64 sums",
             "data": "synthetic",
             "config": {"workload": f"{cfg['name']}: {cfg['desc']}", "containers": n_ctr,
-                       "integrals_per_step": n_int, "variant": "batched (all containers in one "
-                       "call)", "err_mode": "global", "rule": "Clenshaw-Curtis N=4/2N=8",
+                       "integrals_per_step": n_int,
+                       "variant": {"batched": "batched (all containers in one call)",
+                                   "batched_learned": "batched, learned seeding"}[head],
+                       "err_mode": "global", "rule": "Clenshaw-Curtis N=4/2N=8",
                        "regions_per_step": stats[-1]["regions"],
                        "splits_per_step": stats[-1]["splits"]},
-            "roofline": roof}
+            "roofline": roof, "variants": variants}
+    if model is not None:
+        line["seed_model"] = model
 
     if args.variants:
+        ctx.set_seed_model(None)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for p in params:  # plain: one call per flow scale
             ctx.integrate(p[None, :], q, ff, L, P.PP | P.PH, rtol=cfg["rtol"])
         torch.cuda.synchronize()
-        line["variants"] = {"plain_per_scale": n_int / (time.perf_counter() - t1)}
+        variants["plain_per_scale"] = {"value": n_int / (time.perf_counter() - t1)}
 
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)

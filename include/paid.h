@@ -101,9 +101,6 @@ typedef struct {
   void *stream;         /* hipStream_t to run on, or NULL for a private stream */
   int profile;          /* 1: time the region-evaluation launches with HIP
                            events on the context stream (paid_stats.eval_*) */
-  int seed_dmax;        /* learned seeding: deepest level of the seed tree (0..12) */
-  double seed_kappa;    /* learned seeding: a node is split while its predicted
-                           leaf count is >= 4 seed_kappa */
 } paid_config;
 
 /* one parameter row: dispersion, temperature and flow scale */
@@ -131,7 +128,7 @@ typedef struct {
 
 /* Fill *cfg with defaults (device 0, N = 4, batch 8, batch_max 1024, global
  * error, FP64, separable projection, nu = 1e-3, max_regions = 2^18,
- * automatic pool, seed_dmax 8, seed_kappa 2). */
+ * automatic pool). */
 int paid_config_default(paid_config *cfg);
 
 /* Create a context on cfg->device.  *out receives the context (NULL on
@@ -194,8 +191,8 @@ int paid_children_eval(struct paid_ctx *ctx, const paid_params *p, const double 
  *
  * Seed tree: from the predicted counts (n = max(0, 2^y - 1) per cell, summed
  * over the cells a node covers, shared by area below a cell) a node is split
- * while its count is >= 4 seed_kappa and its depth < D; D starts at
- * seed_dmax and is lowered until the tree has at most max_regions/4 leaves.
+ * while its count is >= 4 kappa and its depth < D; D starts at dmax and is
+ * lowered until the tree has at most max_regions/4 leaves.
  * Only the leaves of the seed tree are integrated; the adaptive loop then
  * continues from them.
  */
@@ -205,9 +202,11 @@ int paid_children_eval(struct paid_ctx *ctx, const paid_params *p, const double 
 /* Number of model parameters (67072). */
 long paid_mlp_nparams(void);
 
-/* Use the model `weights` ([paid_mlp_nparams()] FP32, copied) for the
- * seeding of every later paid_integrate call on ctx; NULL turns seeding off. */
-int paid_set_seed_model(struct paid_ctx *ctx, const float *weights);
+/* Use the model `weights` ([paid_mlp_nparams()] FP32, copied, all finite)
+ * for the seeding of every later paid_integrate call on ctx, with depth
+ * bound dmax (0..12) and threshold 4 kappa (kappa > 0); weights NULL turns
+ * seeding off (dmax and kappa are then ignored). */
+int paid_set_seed_model(struct paid_ctx *ctx, const float *weights, int dmax, double kappa);
 
 /* Make every later paid_integrate call on ctx also write, per container in
  * the order of `out`, its model features [n_ctr][7] and the labels of its

@@ -37,8 +37,7 @@ class Config(C.Structure):
                 ("err_mode", C.c_int), ("precision", C.c_int), ("gram", C.c_int),
                 ("kind", C.c_int), ("nu", C.c_double), ("max_regions", C.c_long),
                 ("max_active", C.c_int), ("pool_gib", C.c_double),
-                ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int),
-                ("seed_dmax", C.c_int), ("seed_kappa", C.c_double)]
+                ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int)]
 
 
 class Params(C.Structure):
@@ -100,7 +99,7 @@ def lib():
         L.paid_last_error.restype = C.c_char_p
         L.paid_mlp_nparams.argtypes = []
         L.paid_mlp_nparams.restype = C.c_long
-        L.paid_set_seed_model.argtypes = [vp, vp]
+        L.paid_set_seed_model.argtypes = [vp, vp, C.c_int, C.c_double]
         L.paid_set_label_output.argtypes = [vp, vp, vp]
         L.paid_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
         L.paid_mlp_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int, vp, dp]
@@ -219,15 +218,13 @@ class Context:
         return q2n, er
 
     # ------------------------------------------------------------ learned seeding
-    def set_seed_model(self, weights):
+    def set_seed_model(self, weights, dmax=8, kappa=2.0):
         """Seed later integrate() calls from this model (None: root start)."""
         if weights is None:
-            self._check(lib().paid_set_seed_model(self.h, None), allow_noconv=False)
-            self._seed_w = None
+            self._check(lib().paid_set_seed_model(self.h, None, 0, 1.0), allow_noconv=False)
             return
         w = weights if hasattr(weights, "data_ptr") else np.ascontiguousarray(weights, np.float32)
-        self._check(lib().paid_set_seed_model(self.h, _ptr(w)), allow_noconv=False)
-        self._seed_w = w
+        self._check(lib().paid_set_seed_model(self.h, _ptr(w), dmax, kappa), allow_noconv=False)
 
     def set_label_output(self, features=None, labels=None):
         """Arm per-container features [n][7] and tree labels [n][256] (FP32

@@ -57,6 +57,8 @@ struct paid_ctx {
   // learned seeding
   DevBuf seedw, sfeat, sfold, sy, sact, pyr, seedd, ifill, labtmp;
   bool seed_on = false;
+  int seed_dmax = 8;
+  double seed_kappa = 2.0;
   float *feat_out = nullptr, *lab_out = nullptr;
   int *host_counters = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profile: around the evaluation launch
@@ -316,8 +318,6 @@ int paid_config_default(paid_config *cfg) {
   cfg->pool_gib = 0.0;
   cfg->gauss[2] = 1.0;
   cfg->stream = nullptr;
-  cfg->seed_dmax = 8;
-  cfg->seed_kappa = 2.0;
   return PAID_OK;
 }
 
@@ -342,8 +342,6 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
   if (cfg.max_regions < 16 || cfg.max_regions > (1L << 28))
     return fail(nullptr, PAID_EINVAL, "max_regions must be in [16, 2^28]");
   if (!(cfg.nu >= 0)) return fail(nullptr, PAID_EINVAL, "nu must be >= 0");
-  if (cfg.seed_dmax < 0 || cfg.seed_dmax > 12) return fail(nullptr, PAID_EINVAL, "seed_dmax must be 0..12");
-  if (!(cfg.seed_kappa > 0)) return fail(nullptr, PAID_EINVAL, "seed_kappa must be > 0");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev == 0) return fail(nullptr, PAID_EDEVICE, "no HIP device");
@@ -577,8 +575,8 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
       P.seed_y = c->sy.as<float>();
       P.pyr = c->pyr.as<double>();
       P.seed_d = c->seedd.as<int>();
-      P.seed_dmax = cfg.seed_dmax;
-      P.seed_thresh = 4.0 * cfg.seed_kappa;
+      P.seed_dmax = c->seed_dmax;
+      P.seed_thresh = 4.0 * c->seed_kappa;
       P.seed_limit = cap / 4;
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
@@ -823,7 +821,7 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
 
 long paid_mlp_nparams(void) { return mlp_layout().total; }
 
-int paid_set_seed_model(paid_ctx *c, const float *w) {
+int paid_set_seed_model(paid_ctx *c, const float *w, int dmax, double kappa) {
   if (!c) return PAID_EINVAL;
   c->err.clear();
   HIPCHK(c, hipSetDevice(c->cfg.device));
@@ -831,6 +829,10 @@ int paid_set_seed_model(paid_ctx *c, const float *w) {
     c->seed_on = false;
     return PAID_OK;
   }
+  if (dmax < 0 || dmax > 12) return fail(c, PAID_EINVAL, "dmax must be 0..12");
+  if (!(kappa > 0) || !std::isfinite(kappa)) return fail(c, PAID_EINVAL, "kappa must be > 0");
+  c->seed_dmax = dmax;
+  c->seed_kappa = kappa;
   const long np = mlp_layout().total;
   HIPCHK(c, c->seedw.ensure(sizeof(float) * np));
   HIPCHK(c, hipMemcpyAsync(c->seedw.p, w, sizeof(float) * np, hipMemcpyDefault, c->stream));

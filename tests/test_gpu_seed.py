@@ -66,6 +66,18 @@ def test_mlp_nparams(P):
     assert P.mlp_nparams() == O.mlp_nparams() == 67072
 
 
+def test_seed_model_arguments_are_checked(P):
+    with P.Context() as c:
+        w = np.zeros(P.mlp_nparams(), dtype=np.float32)
+        for dmax, kappa in ((13, 2.0), (-1, 2.0), (8, 0.0), (8, float("nan"))):
+            with pytest.raises(P.PaidError):
+                c.set_seed_model(w, dmax=dmax, kappa=kappa)
+        w[5] = np.inf
+        with pytest.raises(P.PaidError):
+            c.set_seed_model(w)
+        c.set_seed_model(None)
+
+
 @pytest.mark.parametrize("n", [1, 100, 1000])
 def test_mlp_forward_matches_oracle(P, n):
     w = random_weights(11)
@@ -214,8 +226,8 @@ def test_seed_tree_and_sums_match_oracle(P, case):
     p = np.array([[1.0, -0.2, -0.6, 0.07, 0.4]])
     n = len(q) * 2
     lab = np.zeros((n, 256), dtype=np.float32)
-    with P.Context(max_regions=cap, max_active=8, seed_dmax=dmax, seed_kappa=kappa) as c:
-        c.set_seed_model(constant_model(ynet))
+    with P.Context(max_regions=cap, max_active=8) as c:
+        c.set_seed_model(constant_model(ynet), dmax=dmax, kappa=kappa)
         c.set_label_output(None, lab)
         out, _, st, rc = c.integrate(p, q, cfg["ff"], cfg["L"], rtol=1e-6, atol=1e300)
     assert st["seeded"] == n
@@ -254,8 +266,8 @@ def test_seeded_integration_meets_the_gate(P):
     prm = np.array([(1, -0.2, -0.5, 0.05, 0.3), (1, -0.3, -1.0, 0.03, 0.05),
                     (1, -0.1, -0.2, 0.08, 2.0)], dtype=np.float64)
     q = W.q_grid(16)[::53][:4]
-    with P.Context(max_regions=1 << 18, max_active=64, seed_kappa=1.0) as c:
-        c.set_seed_model(random_weights(17, scale=2.0))
+    with P.Context(max_regions=1 << 18, max_active=64) as c:
+        c.set_seed_model(random_weights(17, scale=2.0), kappa=1.0)
         out, _, st, rc = c.integrate(prm, q, cfg["ff"], cfg["L"], rtol=1e-6)
     assert rc == 0 and st["seeded"] > 0
     picks = [(ip, iq, ch) for ip in range(len(prm)) for iq in range(len(q)) for ch in (O.PP, O.PH)]

@@ -94,6 +94,24 @@ def config(name: str, seed: int | None = None) -> dict:
     raise KeyError(name)
 
 
+def c5_training_calls(seed: int = 5, calls: int = 20, rows: int = 16, nq: int = 32):
+    """Training set of the learned seeding: per call, `rows` random parameter
+    rows of the batched workload's distribution with Omega log-uniform in
+    [0.01, 10], and `nq` transfer momenta drawn without replacement from the
+    16 x 16 grid; both channels.  The default gives 10,240 trees per channel."""
+    rng = np.random.default_rng(seed)
+    grid = q_grid(16)
+    out = []
+    for _ in range(calls):
+        mu = rng.uniform(-1.2, 0.0, rows)
+        T = np.exp(rng.uniform(math.log(0.005), math.log(0.1), rows))
+        tp = rng.uniform(-0.35, 0.0, rows)
+        om = np.exp(rng.uniform(math.log(0.01), math.log(10.0), rows))
+        p = np.stack([np.ones(rows), tp, mu, T, om], axis=1)
+        out.append((p, grid[rng.choice(len(grid), nq, replace=False)]))
+    return out
+
+
 def random_params(n: int, seed: int, omega_range=(0.01, 1.0)) -> np.ndarray:
     """Random parameter rows as in the batched workload."""
     rng = np.random.default_rng(seed)
