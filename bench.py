@@ -30,14 +30,17 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64: vector (256 CUs x 4 SIMD x 16 lanes x 2 
 # Algorithmic work of one region-evaluation work item (a parent and its four
 # children, rule pair N = 4 / 2N = 8, shared 17 x 17 node grid), in FP64 flops
 # (an FMA counts 2):
-#   integrand: 289 nodes x 118 (dispersion 12, close-pair switch 8, interval
-#              map 4, three Horner chains of degree 15 = 90, combine 4);
+#   integrand: 289 nodes x 88 (dispersion 12, close-pair switch 8, interval
+#              map 4, two Horner chains of degree 15 = 60, combine 4); a
+#              node needs two chains (two values, or one value and its
+#              divided difference); a third chain that a branch-free
+#              evaluation may compute and discard is not counted;
 #   separable projection with NP = NB(NB+1)/2 axis products, NB = 2L+1:
 #     y-sums  2 x 17 x NP x 27 (fine: 9 mul + 9 FMA) + 2 x 9 x NP x 10 (coarse: 5 FMA)
 #     x-sums  4 children x NP^2 x 42 (fine 9 x (mul + FMA), coarse 5 x (mul + FMA))
 #     pairs   4 children x MB(MB+1)/2 x 3
 #   dense projection (matrix cores): 4 children x 2 M^2 (81 + 25).
-K_FLOPS_PER_NODE = 118
+K_FLOPS_PER_NODE = 88
 NODES_PER_ITEM = 289
 
 
@@ -95,6 +98,10 @@ def main():
     ap.add_argument("--seed-model", default=None,
                     help="model file of the learned seeding (default: the shipped one)")
     ap.add_argument("--no-seed", action="store_true", help="time the plain batched scheme only")
+    ap.add_argument("--tuned", default=None,
+                    help="autotuner profile (JSON) whose config to apply; default: the shipped "
+                         "profile of the workload if there is one")
+    ap.add_argument("--graph", type=int, default=1, help="replay each round as a HIP graph")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (the reference "
                          "for scaling the HBM byte counters) and exit")
@@ -128,8 +135,13 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     prec = {"fp64": P.FP64, "fp32": P.FP32, "bf16x3": P.BF16X3}[args.precision]
-    ctx = P.Context(stream=stream.cuda_stream, profile=1, precision=prec,
-                    gram=P.GRAM_SEPARABLE if args.gram == "separable" else P.GRAM_MFMA)
+    tuned = {}
+    tpath = args.tuned or os.path.join(ROOT, "paid_1610_09991_amd", f"tuned_{args.workload.lower()}.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            tuned = json.load(f)["config"]
+    ctx = P.Context(stream=stream.cuda_stream, profile=1, precision=prec, graph=args.graph,
+                    gram=P.GRAM_SEPARABLE if args.gram == "separable" else P.GRAM_MFMA, **tuned)
     out = torch.empty((len(params), len(q), nch, M, M), dtype=torch.float64, device=dev)
     run = lambda o: ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=o)
 
@@ -207,6 +219,7 @@ def main():
                        "variant": {"batched": "batched (all containers in one call)",
                                    "batched_learned": "batched, learned seeding"}[head],
                        "err_mode": "global", "rule": "Clenshaw-Curtis N=4/2N=8",
+                       "launch": {"graph": args.graph, **(tuned or {"batch": 8, "batch_max": 1024})},
                        "regions_per_step": stats[-1]["regions"],
                        "splits_per_step": stats[-1]["splits"]},
             "roofline": roof, "variants": variants}

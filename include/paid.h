@@ -101,6 +101,10 @@ typedef struct {
   void *stream;         /* hipStream_t to run on, or NULL for a private stream */
   int profile;          /* 1: time the region-evaluation launches with HIP
                            events on the context stream (paid_stats.eval_*) */
+  int graph;            /* 1: capture the device round (seven kernels and the
+                           read-back of three counters, in three parts around
+                           the evaluation launch) as HIP graphs and replay
+                           them every round */
 } paid_config;
 
 /* one parameter row: dispersion, temperature and flow scale */

@@ -37,7 +37,8 @@ class Config(C.Structure):
                 ("err_mode", C.c_int), ("precision", C.c_int), ("gram", C.c_int),
                 ("kind", C.c_int), ("nu", C.c_double), ("max_regions", C.c_long),
                 ("max_active", C.c_int), ("pool_gib", C.c_double),
-                ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int)]
+                ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int),
+                ("graph", C.c_int)]
 
 
 class Params(C.Structure):
@@ -155,9 +156,9 @@ class Context:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().paid_destroy(self.h)
-            self.h = None
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.paid_destroy(self.h)
+        self.h = None
 
     __del__ = close
 

@@ -1,0 +1,93 @@
+"""Autotuner of the batched scheme's launch parameters.
+
+Times `paid_integrate` on a seeded sample of a workload for a grid of
+candidate settings and keeps the fastest: `batch` (the fewest leaves a
+container splits per round: the MaxTask analogue of Listing 2), `batch_max`
+(the most) and `max_active` (containers resident at once; 0 = as many as the
+region pool holds).  Every candidate must give the same answer within the
+tolerance (checked against the first candidate's result), so the tuner only
+trades time.  The result is a small JSON profile:
+
+    python -m paid_1610_09991_amd.autotune --workload C2 --out tuned_c2.json
+
+and `Context(**profile["config"])` applies it.
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sample(cfg, fraction, seed=7):
+    """every parameter row, a seeded subset of the transfer momenta"""
+    rng = np.random.default_rng(seed)
+    q = cfg["q"]
+    k = max(1, int(round(len(q) * fraction)))
+    return cfg["params"], q[np.sort(rng.choice(len(q), k, replace=False))]
+
+
+def tune(workload="C2", fraction=0.25, batches=(4, 8, 16, 32), batch_maxes=(256, 1024, 4096),
+         actives=(0,), repeat=2, log=print):
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    import paid_1610_09991_amd as P
+    import workloads as W
+
+    cfg = W.config(workload)
+    params, q = sample(cfg, fraction)
+    ff, L = cfg["ff"], cfg["L"]
+    M = ff.shape[0]
+    stream = torch.cuda.current_stream()
+    out = torch.empty((len(params), len(q), 2, M, M), dtype=torch.float64, device="cuda")
+    ref = None
+    results = []
+    for b, bm, act in itertools.product(batches, batch_maxes, actives):
+        if bm < b:
+            continue
+        ctx = P.Context(stream=stream.cuda_stream, batch=b, batch_max=bm, max_active=act)
+        best = None
+        for _ in range(repeat):
+            _, _, st, rc = ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=out)
+            best = st["seconds"] if best is None else min(best, st["seconds"])
+        val = out.cpu().numpy()
+        if ref is None:
+            ref = val
+        scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max(axis=(-1, -2), keepdims=True))
+        dev = float(np.max(np.abs(val - ref) / scale)) / cfg["rtol"]
+        results.append({"batch": b, "batch_max": bm, "max_active": act, "seconds": best,
+                        "regions": st["regions"], "deviation_in_rtol": dev})
+        log(f"# batch {b:3d} batch_max {bm:5d} max_active {act}: {best:.4f} s, "
+            f"regions {st['regions']}, |delta| {dev:.2e} rtol")
+        ctx.close()
+    ok = [r for r in results if r["deviation_in_rtol"] <= 2.0]
+    best = min(ok, key=lambda r: r["seconds"])
+    return {"workload": workload, "sample": {"q": len(q), "params": len(params)},
+            "config": {"batch": best["batch"], "batch_max": best["batch_max"],
+                       "max_active": best["max_active"]},
+            "results": results}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--fraction", type=float, default=0.25)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    prof = tune(a.workload, a.fraction)
+    txt = json.dumps(prof, indent=1)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt + "\n")
+    print(json.dumps({"tuned": prof["config"], "workload": a.workload}))
+
+
+if __name__ == "__main__":
+    main()

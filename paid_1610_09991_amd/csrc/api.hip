@@ -159,9 +159,10 @@ Entry make_entry(const paid_params &p, int kind, int &off) {
     e.w = kPiH * p.T;
     e.inv_w = 1.0 / e.w;
     double top = e.emax * 1.01 + 1e-3 * e.w;
-    e.J = 1 + (int)ceil((asinh(top / e.w) - kTabS1) / kTabDs);
-    if (e.J < 1) e.J = 1;
-    double xJ = e.w * sinh(kTabS1 + (e.J - 1) * kTabDs);
+    e.J = tab_rows(top, e.w);
+    double cJ, hJ;
+    tab_interval(e.J - 1, e.w, cJ, hJ);
+    double xJ = cJ + hJ;  // top of the last interval
     double big = fmax(fmax(p.Omega, 1.6 * xJ), kPiH * p.T);
     int nm = (int)ceil((4.0 * big / (kPiH * p.T) - 1.0) / 2.0);
     e.nmats = nm < 8 ? 8 : nm;
@@ -600,18 +601,58 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   const int eval_grid = dev_cus * 16;
   long rounds = 0, eval_items = 0;
   double eval_ms = 0.0;
+  // one device round in three parts: admission, roots, selection and work
+  // list; evaluation; updates, finalisation and the read-back of the three
+  // counters the host needs
+  auto part = [&](int k, hipStream_t st) -> hipError_t {
+    hipError_t e;
+    if (k == 0) {
+      if ((e = launch_admit(P, st)) != hipSuccess) return e;
+      if ((e = launch_root(P, st)) != hipSuccess) return e;
+      if ((e = launch_select(P, st)) != hipSuccess) return e;
+      return launch_worklist(P, st);
+    }
+    if (k == 1) return launch_eval(P, eval_grid, st);
+    if ((e = launch_update(P, st)) != hipSuccess) return e;
+    if ((e = launch_finalize(P, st)) != hipSuccess) return e;
+    return hipMemcpyAsync(c->host_counters, cnt + 4, 12, hipMemcpyDeviceToHost, st);
+  };
+  // with cfg.graph each part is captured once and replayed every round (the
+  // arguments of every launch are the same in every round); the profiling
+  // events are recorded between the parts, outside the graphs
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+  struct GraphGuard {
+    hipGraphExec_t *ge;
+    ~GraphGuard() {
+      for (int k = 0; k < 3; ++k)
+        if (ge[k]) (void)hipGraphExecDestroy(ge[k]);
+    }
+  } gguard{gexec};
+  if (cfg.graph) {
+    for (int k = 0; k < 3; ++k) {
+      hipGraph_t g = nullptr;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+      hipError_t e1 = part(k, c->stream);
+      hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+      if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        HIPCHK(c, e1 != hipSuccess ? e1 : e2);
+      }
+      hipError_t e3 = hipGraphInstantiate(&gexec[k], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(c, e3);
+    }
+  }
+  auto run_part = [&](int k) -> hipError_t {
+    return gexec[k] ? hipGraphLaunch(gexec[k], c->stream) : part(k, c->stream);
+  };
   for (;;) {
-    HIPCHK(c, launch_admit(P, c->stream));
-    HIPCHK(c, launch_root(P, c->stream));
-    HIPCHK(c, launch_select(P, c->stream));
-    HIPCHK(c, launch_worklist(P, c->stream));
+    HIPCHK(c, run_part(0));
     if (cfg.profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_eval(P, eval_grid, c->stream));
+    HIPCHK(c, run_part(1));
     if (cfg.profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-    HIPCHK(c, launch_update(P, c->stream));
-    HIPCHK(c, launch_finalize(P, c->stream));
+    HIPCHK(c, run_part(2));
     ++rounds;
-    HIPCHK(c, hipMemcpyAsync(c->host_counters, cnt + 4, 12, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     eval_items += c->host_counters[2];
     if (cfg.profile) {

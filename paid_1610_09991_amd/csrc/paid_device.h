@@ -23,20 +23,48 @@ constexpr int kMaxMU = kMaxMB * (kMaxMB + 1) / 2;
 //   S(x) = T sum_{n in Z} hdot(w_n) / (i w_n - x),   hdot = d/dOmega theta^2
 // (theta^2 itself for the non-differentiated bubble), because partial
 // fractions give K_ph(a,b) = S[a,b] = (S(a)-S(b))/(a-b) and
-// K_pp(a,b) = -S[a,-b].  S is analytic except at x = +-i w_n, so on each
-// interval of x >= 0 it is a short Taylor series.  Intervals are uniform in
-// s = asinh(x / (pi T)): the half-width of each is one tenth of the distance
-// from its centre to the nearest singularity, which makes degree 15 exact to
-// rounding and lets a divided difference of two close energies be formed on
-// one polynomial without cancellation.
-constexpr int kTabDeg = 15;
-constexpr int kTabStride = 20;                 // c, 1/h, h, pad, coef[16]
-constexpr double kTabDs = 0.2;                 // interval width in s
-constexpr double kTabS1 = 0.09983407889920758; // asinh(0.1): central half-width
+// K_pp(a,b) = -S[a,-b].  S is analytic except at x = +-i w_n, so on short
+// intervals of x >= 0 it is a short Taylor series.  In units of w = pi T
+// (the distance of the nearest singularity from the real axis) the
+// intervals are: 9 central ones centred at 0, 1/8, ..., 1 with half-width
+// 1/16, then 8 per octave, [2^e (1 + m/8), 2^e (1 + (m+1)/8)), m = 0..7, so
+// the index follows from the exponent and top mantissa bits of |x|/w.  Every
+// half-width is at most 1/16 of the distance from its centre to the nearest
+// singularity, which makes degree 13 exact to rounding on the interval (and
+// accurate out to 1.5 half-widths, where the divided difference of two close
+// energies is formed on the polynomial of one of them).
+// Row layout: c, 1/h, coef[14] of P(t) = S(c + h t), two doubles of padding
+// (a 144-byte stride starts consecutive rows on different LDS banks).
+constexpr int kTabDeg = 13;
+constexpr int kTabStride = 18;                 // c, 1/h, coef[14], 2 pad (spreads rows over LDS banks)
+constexpr int kTabCoef = 2;                    // offset of the coefficients in a row
+constexpr int kTabCentral = 9;                 // central intervals
+constexpr int kTabPerOct = 8;                  // intervals per octave above |x| = w
 constexpr int kTabPts = 32;                    // Cauchy points per interval
 constexpr double kTabRho = 2.0;                // Cauchy radius in half-widths
 constexpr int kTabKTail = 24;                  // tail expansion terms
-constexpr double kDdSwitch2 = 0.0025;          // (0.05)^2: close-pair switch
+constexpr double kDdSwitch2 = 0.0004;          // (0.02)^2: close-pair switch
+
+// interval j in units of w: centre c and half-width h (j >= 0)
+__host__ __device__ inline void tab_interval(int j, double w, double &c, double &h) {
+  if (j < kTabCentral) {
+    c = w * (0.125 * j);
+    h = w * 0.0625;
+  } else {
+    const int k = j - kTabCentral, e = k / kTabPerOct, m = k - e * kTabPerOct;
+    const double s = ldexp(w, e);
+    c = s * (1.0 + 0.125 * (m + 0.5));
+    h = s * 0.0625;
+  }
+}
+
+// rows needed to cover |x| <= top
+__host__ __device__ inline int tab_rows(double top, double w) {
+  if (top < w) return kTabCentral;
+  int E = 0;
+  (void)frexp(top / w, &E);  // top/w in [2^(E-1), 2^E)
+  return kTabCentral + kTabPerOct * E;
+}
 
 struct Entry {        // one parameter row
   double t, tp, mu, T, Om;
@@ -64,93 +92,48 @@ __host__ __device__ inline uint64_t code_iy(uint64_t c) { return c & 0xFFFFFFFul
 
 // ---------------------------------------------------------------------------
 // Frequency-sum table evaluation.
+// interval of |x| (no transcendental: exponent and top mantissa bits of |x|/w)
 __device__ inline int tab_index(const Entry &e, double ax) {
-  float v = (float)(ax * e.inv_w);
-  float s = __logf(v + __fsqrt_rn(fmaf(v, v, 1.0f)));
-  int j = (s < (float)kTabS1) ? 0 : 1 + (int)((s - (float)kTabS1) * (float)(1.0 / kTabDs));
+  const float v = (float)(ax * e.inv_w);
+  int j;
+  if (v < 1.0f) {
+    j = (int)fmaf(v, 8.0f, 0.5f);
+  } else {
+    const unsigned int b = __float_as_uint(v);
+    j = kTabCentral + ((int)(b >> 23) - 127) * kTabPerOct + (int)((b >> 20) & 7u);
+  }
   return j < e.J - 1 ? j : e.J - 1;
 }
 
-__device__ inline double tab_poly(const double *cf, double t) {
-  double r = cf[kTabDeg];
-#pragma unroll
-  for (int k = kTabDeg - 1; k >= 0; --k) r = fma(r, t, cf[k]);
-  return r;
-}
-
-// S(x) for any real x (odd function)
-__device__ inline double S_eval(const Entry &e, const double *tab, double x) {
-  double ax = fabs(x);
-  int j = tab_index(e, ax);
-  const double *row = tab + j * kTabStride;
-  if (j == 0) return tab_poly(row + 4, x * row[1]);  // central interval, centred at 0
-  double v = tab_poly(row + 4, (ax - row[0]) * row[1]);
-  return x < 0.0 ? -v : v;
-}
-
-// divided difference S[x, y]
-__device__ inline double S_dd(const Entry &e, const double *tab, double x, double y) {
-  double d = x - y, m = 0.5 * (x + y);
-  if (d * d >= kDdSwitch2 * (m * m + e.w * e.w)) return (S_eval(e, tab, x) - S_eval(e, tab, y)) / d;
-  int j = tab_index(e, fabs(m));
-  const double *row = tab + j * kTabStride;
-  double tx, ty;
-  if (j == 0) {
-    tx = x * row[1];
-    ty = y * row[1];
-  } else {
-    if (m < 0.0) { x = -x; y = -y; }  // S[x,y] = S[-x,-y] for odd S
-    tx = (x - row[0]) * row[1];
-    ty = (y - row[0]) * row[1];
-  }
-  // Horner at tx carries the quotient coefficients; Horner of those at ty is
-  // the divided difference of the polynomial (no subtraction of values).
-  const double *cf = row + 4;
-  double q = cf[kTabDeg], r = 0.0;
-#pragma unroll
-  for (int k = kTabDeg - 1; k >= 0; --k) {
-    r = fma(r, ty, q);
-    q = fma(q, tx, cf[k]);
-  }
-  return r * row[1];
-}
-
-// kernel K_j(a, b): ph = S[a,b], pp = -S[a,-b].  Branch-free in the data:
-// both the two-value and the one-polynomial forms run in the same loop, so
-// lanes of a wavefront never diverge on the node's energies.
+// kernel K_j(a, b): ph = S[a,b], pp = -S[a,-b], with x = a and y = b (ph) or
+// -b (pp).  S is odd and S[x,y] = S[-x,-y], so both are flipped to x >= 0.
+// Far pairs take two values, S[x,y] = (P_jx(tx) - sign(y) P_jy(ty))/(x - y);
+// close pairs (|x - y| < 0.02 sqrt(x^2 + w^2)) take the divided difference on
+// the polynomial of x's interval: Horner at tx carries the quotient
+// coefficients, Horner of those at ty is the divided difference (no
+// subtraction of values; there |ty| <= 1.5, a tenth of the radius of
+// convergence in units of the half-width).  Both forms run in one loop
+// with the second row and argument chosen per lane, so lanes never diverge.
 __device__ inline double K_eval(const Entry &e, const double *tab, int ch, double a, double b) {
-  const double x = a, y = ch ? b : -b;
-  const double d = x - y, m = 0.5 * (x + y);
-  const bool close = d * d < kDdSwitch2 * (m * m + e.w * e.w);
-  const double *rx, *ry;
-  double tx, ty, sx = 1.0, sy = 1.0;
-  if (close) {
-    int j = tab_index(e, fabs(m));
-    rx = ry = tab + j * kTabStride;
-    double xx = x, yy = y;
-    if (j != 0 && m < 0.0) { xx = -x; yy = -y; }  // S[x,y] = S[-x,-y]
-    tx = (xx - rx[0]) * rx[1];
-    ty = (yy - rx[0]) * rx[1];
-  } else {
-    int jx = tab_index(e, fabs(x)), jy = tab_index(e, fabs(y));
-    rx = tab + jx * kTabStride;
-    ry = tab + jy * kTabStride;
-    tx = jx == 0 ? x * rx[1] : (fabs(x) - rx[0]) * rx[1];
-    ty = jy == 0 ? y * ry[1] : (fabs(y) - ry[0]) * ry[1];
-    if (jx != 0 && x < 0.0) sx = -1.0;
-    if (jy != 0 && y < 0.0) sy = -1.0;
-  }
-  // q: Horner at tx on rx; py: Horner at ty on ry; r: Horner at ty of the
-  // quotient coefficients of q, i.e. the divided difference on one polynomial
-  const double *cx = rx + 4, *cy = ry + 4;
+  const double y0 = ch ? b : -b;
+  const double f = a < 0.0 ? -1.0 : 1.0;
+  const double x = f * a, y = f * y0;
+  const double d = x - y;
+  const bool close = d * d < kDdSwitch2 * (x * x + e.w * e.w);
+  const double ay = fabs(y);
+  const double *rx = tab + tab_index(e, x) * kTabStride;
+  const double *ry = close ? rx : tab + tab_index(e, ay) * kTabStride;
+  const double tx = (x - rx[0]) * rx[1];
+  const double ty = ((close ? y : ay) - ry[0]) * ry[1];
+  const double *cx = rx + kTabCoef, *cy = ry + kTabCoef;
   double q = cx[kTabDeg], py = cy[kTabDeg], r = 0.0;
-#pragma unroll 4
+#pragma unroll
   for (int k = kTabDeg - 1; k >= 0; --k) {
     r = fma(r, ty, q);
     q = fma(q, tx, cx[k]);
     py = fma(py, ty, cy[k]);
   }
-  double s = close ? r * rx[1] : (sx * q - sy * py) / d;
+  const double s = close ? r * rx[1] : (q - (y < 0.0 ? -py : py)) / d;
   return ch ? s : -s;
 }
 

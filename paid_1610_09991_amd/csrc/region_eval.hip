@@ -35,7 +35,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
 constexpr double kSqrt2 = 1.41421356237309504880;
-constexpr int kTabRowsLds = 48;  // table rows a workgroup holds in LDS
+constexpr int kTabRowsLds = 96;  // table rows a workgroup holds in LDS
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -652,21 +652,22 @@ __device__ inline int item_slot(const Problem &P, int w) {
   return lo;
 }
 
+// Work item r of slot s: split the selected leaf into its four children.
+// tab: the table of the slot's parameter row (LDS or global memory).
 template <int L, int GRAM>
-__device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int w,
+__device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int s, int r,
                         const double *tab) {
+  const Ctr C = P.ctr[P.cid[s]];
+  const Entry E = P.entries[C.entry];
   // the pool and the deltas hold P.MU form-factor pairs (<= the box pairs)
   constexpr int KMAX = (Dims<L>::MU + 63) / 64;
   const int MU = P.MU;
   const int lane = lane_id();
-  const int s = item_slot(P, w), r = w - P.woff[s];
   const long leaf = P.sel[(long)s * P.bmax + r];
   const long nold = P.nleaf[s];
   const long pbase = (long)s * P.cap + leaf;
   const uint64_t pc = P.code[pbase];
   const double pkey = P.key[pbase];
-  const Ctr C = P.ctr[P.cid[s]];
-  const Entry E = P.entries[C.entry];
   // delta of the container sums: minus the parent, plus its children
   double dv[KMAX], dp[KMAX];
 #pragma unroll
@@ -732,55 +733,60 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int 
   }
 }
 
-// Work items are processed in groups (one per wave); each workgroup takes a
-// contiguous range of groups, so consecutive groups mostly belong to the same
-// container and parameter row and the LDS table is loaded once per range.
+// Each workgroup takes a contiguous range of work items; its waves take every
+// nw-th item of it, so at any time they work on neighbouring parents, mostly
+// of one container and parameter row.  The LDS holds the table of the
+// parameter row of the range's first item (loaded once; items of another
+// row read their table from global memory), and there is no workgroup
+// barrier in the item loop: each wave runs through its items on its own.
+// The slot of an item is found by a search only when the wave's items leave
+// the current slot's range.
 template <int L, int GRAM>
 __global__ void __launch_bounds__(256) k_children(Problem P) {
   extern __shared__ double lds_raw[];
   __shared__ int pidmap[Dims<L>::MU];
-  __shared__ int s_loaded, s_need;
+  __shared__ int s_entry;
   double *tabl = lds_raw;
   // the wave index is uniform in a wave: keep it (and all per-item
   // bookkeeping derived from it) in scalar registers
   const int nw = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw + kTabRowsLds * kTabStride +
                                                   (size_t)wv * P.lds_wave_doubles);
-  build_pidmap<L>(pidmap, threadIdx.x, blockDim.x);
-  if (threadIdx.x == 0) s_loaded = -1;
-  __syncthreads();
   const int total = P.counters[2];
-  const int ngroups = (total + nw - 1) / nw;
-  const int gper = (ngroups + gridDim.x - 1) / gridDim.x;
-  const int g0 = blockIdx.x * gper, g1 = min(g0 + gper, ngroups);
+  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int i0 = blockIdx.x * per, i1 = min(i0 + per, total);
+  if (i0 >= i1) return;  // uniform in the workgroup
+  build_pidmap<L>(pidmap, threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0) {
+    const int e0 = P.ctr[P.cid[item_slot(P, i0)]].entry;
+    s_entry = (P.entries[e0].J <= kTabRowsLds) ? e0 : -1;
+  }
+  __syncthreads();
+  const int ent = s_entry;
+  if (ent >= 0) {
+    const Entry E0 = P.entries[ent];
+    const double *src = P.tab + E0.tab_off;
+    for (int i = threadIdx.x; i < E0.J * kTabStride; i += blockDim.x) tabl[i] = src[i];
+  }
+  __syncthreads();
+  int s = -1, lo = 0, hi = 0;  // current slot and its item range [lo, hi)
 #pragma unroll 1
-  for (int g = g0; g < g1; ++g) {
-    // the parameter row of the group's first item decides the LDS table
-    if (threadIdx.x == 0) {
-      int w0 = g * nw;
-      int e0 = P.ctr[P.cid[item_slot(P, w0)]].entry;
-      s_need = (P.entries[e0].J <= kTabRowsLds) ? e0 : -1;
+  for (int w = i0 + wv; w < i1; w += nw) {
+    if (w >= hi) {  // find the slot holding item w (woff is non-decreasing)
+      int a = s < 0 ? 0 : s + 1, b = P.W;  // woff[a] <= w < woff[b]
+      while (b - a > 1) {
+        const int mid = (a + b) >> 1;
+        if (P.woff[mid] <= w) a = mid; else b = mid;
+      }
+      s = a;
+      lo = P.woff[s];
+      hi = P.woff[s + 1];
     }
-    __syncthreads();
-    const int need = s_need, loaded = s_loaded;
-    if (need >= 0 && need != loaded) {
-      const Entry E0 = P.entries[need];
-      const double *src = P.tab + E0.tab_off;
-      for (int i = threadIdx.x; i < E0.J * kTabStride; i += blockDim.x) tabl[i] = src[i];
-      __syncthreads();
-      if (threadIdx.x == 0) s_loaded = need;
-    }
-    __syncthreads();
-    const int w = g * nw + wv;
-    if (w < total) {
-      int s = item_slot(P, w);
-      int e = P.ctr[P.cid[s]].entry;
-      if (e == s_loaded)
-        do_item<L, GRAM>(S, P, pidmap, w, tabl);
-      else
-        do_item<L, GRAM>(S, P, pidmap, w, P.tab + P.entries[e].tab_off);
-    }
-    __syncthreads();
+    const int e = P.ctr[P.cid[s]].entry;
+    if (e == ent)
+      do_item<L, GRAM>(S, P, pidmap, s, w - lo, tabl);
+    else
+      do_item<L, GRAM>(S, P, pidmap, s, w - lo, P.tab + P.entries[e].tab_off);
   }
 }
 

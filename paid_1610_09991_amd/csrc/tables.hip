@@ -50,16 +50,6 @@ __global__ void k_zeta(const Entry *entries, int n, double *zeta) {
   zeta[e * (kTabKTail + 1) + k] = z;
 }
 
-__device__ inline void interval(const Entry &E, int j, double &c, double &h) {
-  if (j == 0) {
-    c = 0.0;
-    h = E.w * sinh(kTabS1);
-  } else {
-    double lo = E.w * sinh(kTabS1 + (j - 1) * kTabDs), hi = E.w * sinh(kTabS1 + j * kTabDs);
-    c = 0.5 * (lo + hi);
-    h = 0.5 * (hi - lo);
-  }
-}
 
 // S(z) at one complex point
 __device__ double2 S_complex(const Entry &E, const double *zeta, double zr, double zi) {
@@ -107,7 +97,7 @@ __global__ void k_tab_points(TabArgs a) {
   const Entry E = a.entries[e];
   if (j >= E.J || E.kind > 1) return;
   double c, h;
-  interval(E, j, c, h);
+  tab_interval(j, E.w, c, h);
   double th = 2.0 * kPi * p / kTabPts, sn, cs;
   sincos(th, &sn, &cs);
   double zr = c + kTabRho * h * cs, zi = kTabRho * h * sn;
@@ -125,12 +115,10 @@ __global__ void k_tab_coef(TabArgs a) {
   if (j >= E.J) return;
   double *row = a.tab + E.tab_off + (long)j * kTabStride;
   double c, h;
-  interval(E, j, c, h);
+  tab_interval(j, E.w, c, h);
   if (k == 0) {
     row[0] = c;
     row[1] = 1.0 / h;
-    row[2] = h;
-    row[3] = 0.0;
   }
   double coef = 0.0;
   if (E.kind <= 1 && !(j == 0 && (k & 1) == 0)) {  // S is odd: even terms vanish at 0
@@ -143,7 +131,7 @@ __global__ void k_tab_coef(TabArgs a) {
     }
     coef = s / kTabPts / pow(kTabRho, (double)k);
   }
-  row[4 + k] = coef;
+  row[kTabCoef + k] = coef;
 }
 
 }  // namespace

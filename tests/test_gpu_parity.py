@@ -294,3 +294,21 @@ def test_reduced_precision_integrals(P, prec):
                 for k, (ip, iq, c) in enumerate(W.containers(cfg)))
     print(f"{prec}: worst integral error {worst:.2e} (gate units of rtol = 1)")
     assert worst <= 2e-5
+
+
+def test_graph_replayed_rounds_match_eager_rounds(P):
+    """Rounds replayed from one captured HIP graph give bit-identical results
+    and statistics to rounds launched one kernel at a time, call after call,
+    with other work on the device in between (fewer slots than containers,
+    so admission runs in many rounds)."""
+    cfg = W.config("C1")
+    args = (cfg["params"], cfg["q"], cfg["ff"], cfg["L"])
+    with P.Context(max_regions=1 << 14, max_active=24) as eager, \
+            P.Context(max_regions=1 << 14, max_active=24, graph=1) as graph:
+        ref, eref, sref, _ = eager.integrate(*args, rtol=1e-5, err=True)
+        for rep in range(3):
+            got, egot, sgot, _ = graph.integrate(*args, rtol=1e-5, err=True)
+            assert np.array_equal(got, ref) and np.array_equal(egot, eref), rep
+            for k in ("regions", "splits", "kernel_evals", "rounds", "launch_rounds"):
+                assert sgot[k] == sref[k], (rep, k)
+            eager.integrate(cfg["params"], cfg["q"][:5], cfg["ff"], cfg["L"], rtol=1e-4)
