@@ -30,17 +30,35 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64: vector (256 CUs x 4 SIMD x 16 lanes x 2 
 # Algorithmic work of one region-evaluation work item (a parent and its four
 # children, rule pair N = 4 / 2N = 8, shared 17 x 17 node grid), in FP64 flops
 # (an FMA counts 2):
-#   integrand: 289 nodes x 88 (dispersion 12, close-pair switch 8, interval
-#              map 4, two Horner chains of degree 15 = 60, combine 4); a
-#              node needs two chains (two values, or one value and its
-#              divided difference); a third chain that a branch-free
-#              evaluation may compute and discard is not counted;
+#   integrand: 289 nodes x 80 (dispersion 12, close-pair switch 8, interval
+#              arguments 4, two Horner chains of degree 13 = 52, combine 4);
+#              a node needs two chains (two values, or one value and its
+#              divided difference); the third chain that the branch-free
+#              evaluation computes and discards is not counted;
 #   separable projection with NP = NB(NB+1)/2 axis products, NB = 2L+1:
 #     y-sums  2 x 17 x NP x 27 (fine: 9 mul + 9 FMA) + 2 x 9 x NP x 10 (coarse: 5 FMA)
 #     x-sums  4 children x NP^2 x 42 (fine 9 x (mul + FMA), coarse 5 x (mul + FMA))
 #     pairs   4 children x MB(MB+1)/2 x 3
 #   dense projection (matrix cores): 4 children x 2 M^2 (81 + 25).
-K_FLOPS_PER_NODE = 88
+K_FLOPS_PER_NODE = 80
+
+# HBM bytes per work item of the region-evaluation kernel, from the
+# FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
+# (profiles/k_children_c2_counters.md); valid only for the kernel sources
+# they were taken with, identified by this hash of csrc/*.hip and csrc/*.h.
+TRAFFIC_BYTES_PER_ITEM = 2410
+TRAFFIC_SOURCES_SHA256 = "b97afb0a69182386a3681c75a94210b306355f9f41c617752c58f4f88f488625"
+
+
+def kernel_sources_sha256() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paid_1610_09991_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(d, "*.hip")) + glob.glob(os.path.join(d, "*.h"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 NODES_PER_ITEM = 289
 
 
@@ -202,8 +220,12 @@ def main():
     flops_launch = fpi * items / max(launches, 1)
     avg_launch = ev_s / max(launches, 1)
     achieved = flops_launch / avg_launch / 1e12 if avg_launch > 0 else 0.0
+    traffic = None
+    if sep and M == 9 and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256:
+        traffic = TRAFFIC_BYTES_PER_ITEM * items / max(launches, 1)
     roof = {"bound": "alu" if sep else "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+            "traffic_unit": "B per launch",
             "kernel": "k_children (region evaluation, %s projection)" %
                       ("separable FP64" if sep else "FP64 matrix-core"),
             "launches": launches, "avg_launch_ms": 1e3 * avg_launch, "flops_per_item": fpi,
