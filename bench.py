@@ -120,6 +120,9 @@ def main():
                     help="autotuner profile (JSON) whose config to apply; default: the shipped "
                          "profile of the workload if there is one")
     ap.add_argument("--graph", type=int, default=1, help="replay each round as a HIP graph")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="with a reduced precision: integrate the workload once more in FP64 and "
+                         "report the deviation of every integral in units of the gate")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (the reference "
                          "for scaling the HBM byte counters) and exit")
@@ -247,6 +250,23 @@ def main():
             "roofline": roof, "variants": variants}
     if model is not None:
         line["seed_model"] = model
+
+    if args.compare_fp64 and args.precision != "fp64":
+        red = out.cpu().numpy()
+        ref_ctx = P.Context(stream=stream.cuda_stream, graph=args.graph, **tuned)
+        ref = torch.empty_like(out)
+        ref_ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=ref)
+        torch.cuda.synchronize()
+        r = ref.cpu().numpy().reshape(-1, M, M)
+        d = np.abs(red.reshape(-1, M, M) - r)
+        scale = np.maximum(np.abs(r), 1e-3 * np.abs(r).max(axis=(1, 2), keepdims=True))
+        g = (d / (cfg["rtol"] * scale)).ravel()
+        line["error_vs_fp64"] = {"integrals": int(g.size), "gate_units_max": float(g.max()),
+                                 "gate_units_median": float(np.median(g)),
+                                 "gate_units_p999": float(np.quantile(g, 0.999)),
+                                 "note": "|x - x_fp64| / (rtol max(|x_fp64|, 1e-3 max|x_fp64| of "
+                                         "the container)) over every integral"}
+        ref_ctx.close()
 
     if args.variants:
         ctx.set_seed_model(None)
