@@ -249,6 +249,18 @@ int paid_train_opts_default(paid_train_opts *o);
 int paid_seed_train(struct paid_ctx *ctx, const float *x, const float *y, int n,
                     const paid_train_opts *opts, float *w, double *loss_hist);
 
+/* The contraction beside the integration (Sec. 2, Eqs. matmul-P, matmul-C,
+ * matmul-D), per transfer momentum l:
+ *   dP = V^P chi^pp V^P,   dC = -V^C chi^ph V^C,
+ *   dD = 2 V^D chi^ph V^D - V^C chi^ph V^D - V^D chi^ph V^C,
+ * on the FP64 matrix cores.
+ *   chi  [n_l][2][M][M]: both channels, pp first (the layout paid_integrate
+ *        writes with channels PAID_PP | PAID_PH, n_l = n_params * n_q)
+ *   VP, VC, VD, dP, dC, dD  [n_l][M][M] FP64 row-major
+ * 1 <= M <= 32, n_l >= 0.  Host or device pointers. */
+int paid_contract(struct paid_ctx *ctx, int n_l, int M, const double *chi, const double *VP,
+                  const double *VC, const double *VD, double *dP, double *dC, double *dD);
+
 /* Release the context and everything it owns.  NULL is accepted. */
 void paid_destroy(struct paid_ctx *ctx);
 

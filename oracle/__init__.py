@@ -272,3 +272,17 @@ def seed_tree(count, dmax, thresh, limit):
     rects = np.zeros((max(n, 1), 4))
     lib().po_seed_tree(_dp(cnt), dmax, thresh, limit, _dp(rects), C.byref(d))
     return n, rects[:n], d.value
+
+
+# ---------------------------------------------------------------- contraction
+def contract(chi, VP, VC, VD):
+    """The contraction beside the integration (Sec. 2, Eqs. matmul-P, matmul-C,
+    matmul-D) as written, per transfer momentum, in FP64 with numpy's matrix
+    product: chi [n_l][2][M][M] (pp, ph), couplings [n_l][M][M]."""
+    chi = np.asarray(chi, dtype=np.float64)
+    pp, ph = chi[:, 0], chi[:, 1]
+    VP, VC, VD = (np.asarray(a, dtype=np.float64) for a in (VP, VC, VD))
+    dP = VP @ pp @ VP
+    dC = -(VC @ ph @ VC)
+    dD = 2.0 * (VD @ ph @ VD) - VC @ ph @ VD - VD @ ph @ VC
+    return dP, dC, dD

@@ -67,7 +67,8 @@ MLP_IN, MLP_OUT = 7, 256
 EXPORTS = ("paid_config_default", "paid_create", "paid_integrate", "paid_kernel_eval",
            "paid_children_eval", "paid_destroy", "paid_last_error", "paid_mlp_nparams",
            "paid_set_seed_model", "paid_set_label_output", "paid_mlp_forward",
-           "paid_mlp_loss_grad", "paid_mlp_adam", "paid_train_opts_default", "paid_seed_train")
+           "paid_mlp_loss_grad", "paid_mlp_adam", "paid_train_opts_default", "paid_seed_train",
+           "paid_contract")
 
 _lib = None
 
@@ -107,6 +108,7 @@ def lib():
         L.paid_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float]
         L.paid_train_opts_default.argtypes = [C.POINTER(TrainOpts)]
         L.paid_seed_train.argtypes = [vp, vp, vp, C.c_int, C.POINTER(TrainOpts), vp, vp]
+        L.paid_contract.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -272,6 +274,22 @@ class Context:
         self._check(lib().paid_seed_train(self.h, _ptr(x), _ptr(y), x.shape[0], C.byref(o), _ptr(w),
                                           _ptr(hist)), allow_noconv=False)
         return w, hist
+
+
+    # ------------------------------------------------------------ contraction
+    def contract(self, chi, VP, VC, VD):
+        """dP, dC, dD of Eqs. matmul-P/C/D for chi [n_l][2][M][M] (pp, ph) and
+        couplings [n_l][M][M]; numpy in, numpy out (or device tensors)."""
+        n_l, M = VP.shape[0], VP.shape[-1]
+        if hasattr(VP, "data_ptr"):
+            import torch
+            outs = [torch.empty_like(VP) for _ in range(3)]
+        else:
+            chi, VP, VC, VD = (_f64(a) for a in (chi, VP, VC, VD))
+            outs = [np.zeros((n_l, M, M)) for _ in range(3)]
+        self._check(lib().paid_contract(self.h, n_l, M, _ptr(chi), _ptr(VP), _ptr(VC), _ptr(VD),
+                                        *[_ptr(o) for o in outs]), allow_noconv=False)
+        return tuple(outs)
 
 
 def mlp_nparams() -> int:

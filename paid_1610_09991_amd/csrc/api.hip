@@ -1079,4 +1079,32 @@ int paid_seed_train(paid_ctx *c, const float *x, const float *y, int n, const pa
   return PAID_OK;
 }
 
+int paid_contract(paid_ctx *c, int n_l, int M, const double *chi, const double *VP,
+                  const double *VC, const double *VD, double *dP, double *dC, double *dD) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if (n_l < 0 || M < 1 || M > 32) return fail(c, PAID_EINVAL, "need n_l >= 0 and 1 <= M <= 32");
+  if (n_l == 0) return PAID_OK;
+  if (!chi || !VP || !VC || !VD || !dP || !dC || !dD) return fail(c, PAID_EINVAL, "NULL array");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  const size_t n = (size_t)n_l * M * M;
+  DevBuf tc, tp, tcc, td, o1, o2, o3;
+  const double *dchi, *dvp, *dvc, *dvd;
+  double *rp, *rc, *rd;
+  int rc_;
+  if ((rc_ = stage_in(c, chi, 2 * n, tc, dchi)) != PAID_OK) return rc_;
+  if ((rc_ = stage_in(c, VP, n, tp, dvp)) != PAID_OK) return rc_;
+  if ((rc_ = stage_in(c, VC, n, tcc, dvc)) != PAID_OK) return rc_;
+  if ((rc_ = stage_in(c, VD, n, td, dvd)) != PAID_OK) return rc_;
+  if ((rc_ = stage_out(c, dP, n, o1, rp)) != PAID_OK) return rc_;
+  if ((rc_ = stage_out(c, dC, n, o2, rc)) != PAID_OK) return rc_;
+  if ((rc_ = stage_out(c, dD, n, o3, rd)) != PAID_OK) return rc_;
+  HIPCHK(c, launch_contract(n_l, M, dchi, dvp, dvc, dvd, rp, rc, rd, c->stream));
+  if ((rc_ = finish_out(c, dP, rp, n)) != PAID_OK) return rc_;
+  if ((rc_ = finish_out(c, dC, rc, n)) != PAID_OK) return rc_;
+  if ((rc_ = finish_out(c, dD, rd, n)) != PAID_OK) return rc_;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PAID_OK;
+}
+
 }  // extern "C"

@@ -168,4 +168,8 @@ hipError_t mlp_gather(const float *X, const float *Y, const int *idx, const int 
                       float *Xb, float *Yb, hipStream_t s);
 hipError_t mlp_count(int *c, hipStream_t s);
 
+// ------------------------------------------------------------------ contraction
+hipError_t launch_contract(int n_l, int M, const double *chi, const double *VP, const double *VC,
+                           const double *VD, double *dP, double *dC, double *dD, hipStream_t s);
+
 }  // namespace paid
