@@ -261,6 +261,38 @@ int paid_seed_train(struct paid_ctx *ctx, const float *x, const float *y, int n,
 int paid_contract(struct paid_ctx *ctx, int n_l, int M, const double *chi, const double *VP,
                   const double *VC, const double *VD, double *dP, double *dC, double *dD);
 
+/* A flow driver over the scale (the flow equations of Sec. 2 with the
+ * couplings held fixed): integrates
+ *   dP/dOmega = V^P chidot^pp V^P,  dC/dOmega = -V^C chidot^ph V^C,
+ *   dD/dOmega = 2 V^D chidot^ph V^D - V^C chidot^ph V^D - V^D chidot^ph V^C
+ * from omega0 to omega1 (either direction) with the Dormand-Prince 5(4)
+ * pair and step-size control in ln Omega; every stage is one batched
+ * paid_integrate of all transfer momenta and both channels followed by
+ * paid_contract.  The context's kind must be PAID_BUBBLE_DOT.
+ *   base  t, tp, mu, T of the parameter row (its Omega is ignored)
+ *   q [n_q][2], ff, n_ff, ff_L: as for paid_integrate
+ *   VP, VC, VD [n_q][n_ff][n_ff]; P, C, D [n_q][n_ff][n_ff] in: the state at
+ *   omega0, out: at omega1.  Host pointers. */
+typedef struct {
+  double omega0, omega1;  /* > 0 */
+  double rtol, atol;      /* step control: max |err| <= atol + rtol max |state| */
+  double rtol_int;        /* tolerance of each integration (<= rtol / 10 advised) */
+  double h0;              /* first step in ln Omega (0: automatic) */
+  int max_steps;
+} paid_flow_opts;
+
+typedef struct {
+  int steps, rejected, evaluations;  /* accepted and rejected steps, integrations */
+  long kernel_evals;                 /* integrand evaluations of all integrations */
+  double seconds;
+} paid_flow_stats;
+
+int paid_flow_opts_default(paid_flow_opts *o);
+int paid_flow(struct paid_ctx *ctx, const paid_params *base, const double *q, int n_q,
+              const double *ff, int n_ff, int ff_L, const double *VP, const double *VC,
+              const double *VD, double *P, double *C, double *D, const paid_flow_opts *opts,
+              paid_flow_stats *stats);
+
 /* Release the context and everything it owns.  NULL is accepted. */
 void paid_destroy(struct paid_ctx *ctx);
 

@@ -57,6 +57,20 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FlowOpts(C.Structure):
+    _fields_ = [("omega0", C.c_double), ("omega1", C.c_double), ("rtol", C.c_double),
+                ("atol", C.c_double), ("rtol_int", C.c_double), ("h0", C.c_double),
+                ("max_steps", C.c_int)]
+
+
+class FlowStats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("rejected", C.c_int), ("evaluations", C.c_int),
+                ("kernel_evals", C.c_long), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class TrainOpts(C.Structure):
     _fields_ = [("steps", C.c_int), ("batch", C.c_int), ("lr", C.c_float), ("lr_final", C.c_float),
                 ("seed", C.c_ulonglong), ("init", C.c_int), ("use_graph", C.c_int)]
@@ -68,7 +82,7 @@ EXPORTS = ("paid_config_default", "paid_create", "paid_integrate", "paid_kernel_
            "paid_children_eval", "paid_destroy", "paid_last_error", "paid_mlp_nparams",
            "paid_set_seed_model", "paid_set_label_output", "paid_mlp_forward",
            "paid_mlp_loss_grad", "paid_mlp_adam", "paid_train_opts_default", "paid_seed_train",
-           "paid_contract")
+           "paid_contract", "paid_flow_opts_default", "paid_flow")
 
 _lib = None
 
@@ -109,6 +123,9 @@ def lib():
         L.paid_train_opts_default.argtypes = [C.POINTER(TrainOpts)]
         L.paid_seed_train.argtypes = [vp, vp, vp, C.c_int, C.POINTER(TrainOpts), vp, vp]
         L.paid_contract.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+        L.paid_flow_opts_default.argtypes = [C.POINTER(FlowOpts)]
+        L.paid_flow.argtypes = [vp, vp, vp, C.c_int, vp, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp,
+                                C.POINTER(FlowOpts), C.POINTER(FlowStats)]
         _lib = L
     return _lib
 
@@ -290,6 +307,29 @@ class Context:
         self._check(lib().paid_contract(self.h, n_l, M, _ptr(chi), _ptr(VP), _ptr(VC), _ptr(VD),
                                         *[_ptr(o) for o in outs]), allow_noconv=False)
         return tuple(outs)
+
+
+    # ------------------------------------------------------------ flow driver
+    def flow(self, base, q, ff, ff_L, VP, VC, VD, P0, C0, D0, **opts):
+        """Integrate the flow (fixed couplings) from omega0 to omega1; returns
+        (P, C, D, stats).  base: (t, t', mu, T)."""
+        o = FlowOpts()
+        lib().paid_flow_opts_default(C.byref(o))
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown flow option {k}")
+            setattr(o, k, v)
+        prm = params_array([tuple(base) + (0.0,)])
+        qa = _f64(q).reshape(-1, 2)
+        ffa = _f64(ff)
+        V = [_f64(v) for v in (VP, VC, VD)]
+        st = [np.array(_f64(x), copy=True) for x in (P0, C0, D0)]
+        fs = FlowStats()
+        self._check(lib().paid_flow(self.h, _ptr(prm), _ptr(qa), qa.shape[0], _ptr(ffa),
+                                    ffa.shape[0], ff_L, *[_ptr(v) for v in V],
+                                    *[_ptr(x) for x in st], C.byref(o), C.byref(fs)),
+                    allow_noconv=False)
+        return st[0], st[1], st[2], fs.as_dict()
 
 
 def mlp_nparams() -> int:

@@ -1107,4 +1107,117 @@ int paid_contract(paid_ctx *c, int n_l, int M, const double *chi, const double *
   return PAID_OK;
 }
 
+int paid_flow_opts_default(paid_flow_opts *o) {
+  if (!o) return PAID_EINVAL;
+  memset(o, 0, sizeof *o);
+  o->omega0 = 1.0;
+  o->omega1 = 0.1;
+  o->rtol = 1e-6;
+  o->atol = 0.0;
+  o->rtol_int = 1e-8;
+  o->h0 = 0.0;
+  o->max_steps = 200;
+  return PAID_OK;
+}
+
+int paid_flow(paid_ctx *c, const paid_params *base, const double *q, int n_q, const double *ff,
+              int n_ff, int ff_L, const double *VP, const double *VC, const double *VD, double *P,
+              double *C, double *D, const paid_flow_opts *oin, paid_flow_stats *stats) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  paid_flow_opts o;
+  if (oin) o = *oin; else paid_flow_opts_default(&o);
+  if (!base || !q || !ff || !VP || !VC || !VD || !P || !C || !D || n_q < 1 || n_ff < 1 || n_ff > 32)
+    return fail(c, PAID_EINVAL, "bad arguments");
+  if (!(o.omega0 > 0) || !(o.omega1 > 0) || !(o.rtol >= 0) || !(o.atol >= 0) ||
+      !(o.rtol > 0 || o.atol > 0) || !(o.rtol_int > 0) || o.max_steps < 1)
+    return fail(c, PAID_EINVAL, "bad flow options");
+  if (c->cfg.kind != PAID_BUBBLE_DOT) return fail(c, PAID_EINVAL, "the flow needs kind PAID_BUBBLE_DOT");
+  const int M = n_ff;
+  const size_t nm = (size_t)n_q * M * M, ny = 3 * nm;  // state: P, C, D
+  std::vector<double> y(ny), V(ny);
+  memcpy(y.data(), P, sizeof(double) * nm);
+  memcpy(y.data() + nm, C, sizeof(double) * nm);
+  memcpy(y.data() + 2 * nm, D, sizeof(double) * nm);
+  memcpy(V.data(), VP, sizeof(double) * nm);
+  memcpy(V.data() + nm, VC, sizeof(double) * nm);
+  memcpy(V.data() + 2 * nm, VD, sizeof(double) * nm);
+  std::vector<double> chi(2 * nm), rhs(ny);
+  paid_flow_stats st;
+  memset(&st, 0, sizeof st);
+  // f(s) = dy/d(ln Omega) = Omega dy/dOmega at Omega = e^s (independent of y)
+  auto f = [&](double s, double *out) -> int {
+    paid_params p = *base;
+    p.Omega = exp(s);
+    paid_stats is;
+    int rc = paid_integrate(c, &p, 1, q, n_q, ff, n_ff, ff_L, PAID_PP | PAID_PH, o.rtol_int, 0.0,
+                            chi.data(), nullptr, &is);
+    if (rc == PAID_ENOCONV)
+      return fail(c, PAID_ENOCONV, "flow: the integration at Omega = %g hit max_regions", p.Omega);
+    if (rc != PAID_OK) return rc;
+    st.evaluations++;
+    st.kernel_evals += is.kernel_evals;
+    rc = paid_contract(c, n_q, M, chi.data(), V.data(), V.data() + nm, V.data() + 2 * nm, out,
+                       out + nm, out + 2 * nm);
+    if (rc != PAID_OK) return rc;
+    for (size_t i = 0; i < ny; ++i) out[i] *= p.Omega;
+    return PAID_OK;
+  };
+  // Dormand-Prince 5(4): nodes, stage weights, 5th-order and 4th-order weights
+  static const double cc[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+  static const double b5[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0.0};
+  static const double b4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
+                               187.0 / 2100, 1.0 / 40};
+  const double s0 = log(o.omega0), s1 = log(o.omega1), dir = s1 >= s0 ? 1.0 : -1.0;
+  double s = s0;
+  double h = o.h0 > 0 ? dir * o.h0 : 0.1 * (s1 - s0);
+  if (h == 0.0) {
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return PAID_OK;
+  }
+  std::vector<std::vector<double>> k(7, std::vector<double>(ny));
+  int rc = f(s, k[0].data());
+  if (rc != PAID_OK) return rc;
+  while (dir * (s1 - s) > 1e-14 * fabs(s1 - s0)) {
+    if (st.steps + st.rejected >= o.max_steps)
+      return fail(c, PAID_ENOCONV, "flow: %d steps without reaching omega1", o.max_steps);
+    if (dir * (s + h - s1) > 0) h = s1 - s;
+    // the right-hand side does not depend on the state: stages are f(s + c h)
+    for (int i = 1; i < 7; ++i)
+      if ((rc = f(s + cc[i] * h, k[i].data())) != PAID_OK) return rc;
+    double emax = 0.0, ymax = 0.0;
+    std::vector<double> yn(ny);
+    for (size_t j = 0; j < ny; ++j) {
+      double d5 = 0.0, d4 = 0.0;
+      for (int i = 0; i < 7; ++i) {
+        d5 += b5[i] * k[i][j];
+        d4 += b4[i] * k[i][j];
+      }
+      yn[j] = y[j] + h * d5;
+      emax = fmax(emax, fabs(h * (d5 - d4)));
+      ymax = fmax(ymax, fmax(fabs(y[j]), fabs(yn[j])));
+    }
+    const double tol = o.atol + o.rtol * ymax;
+    const double ratio = tol > 0 ? emax / tol : (emax > 0 ? 1e300 : 0.0);
+    if (ratio <= 1.0) {
+      y.swap(yn);
+      s += h;
+      st.steps++;
+      k[0].swap(k[6]);  // first same as last
+    } else {
+      st.rejected++;
+    }
+    const double fac = ratio > 0 ? 0.9 * pow(ratio, -0.2) : 5.0;
+    h *= fmin(5.0, fmax(0.2, fac));
+  }
+  memcpy(P, y.data(), sizeof(double) * nm);
+  memcpy(C, y.data() + nm, sizeof(double) * nm);
+  memcpy(D, y.data() + 2 * nm, sizeof(double) * nm);
+  st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  return PAID_OK;
+}
+
 }  // extern "C"

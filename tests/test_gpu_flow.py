@@ -1,0 +1,43 @@
+"""The flow driver (Dormand-Prince 5(4) over ln Omega, every stage one
+batched integration plus the contraction) against a closed form: with the
+couplings held fixed the flow is a quadrature in Omega, so
+P(Omega1) - P(Omega0) = V^P [chi^pp(Omega1) - chi^pp(Omega0)] V^P and likewise
+C and D, with chi the non-differentiated regulated bubble, which the oracle
+integrates on its own."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_flow_matches_bubble_differences():
+    import paid_1610_09991_amd as P
+    cfg = W.config("C1")
+    t, tp, mu, T, _ = cfg["params"][0]
+    q = cfg["q"][[5, 21, 42]]
+    M = 5
+    rng = np.random.default_rng(9)
+    V = [rng.normal(size=(len(q), M, M)) for _ in range(3)]
+    S0 = [rng.normal(size=(len(q), M, M)) for _ in range(3)]
+    om0, om1 = 1.0, 0.1
+    with P.Context(max_regions=1 << 19, max_active=6) as ctx:
+        Pf, Cf, Df, st = ctx.flow((t, tp, mu, T), q, cfg["ff"], cfg["L"], *V, *S0,
+                                  omega0=om0, omega1=om1, rtol=1e-8, rtol_int=1e-11)
+    assert st["steps"] >= 2 and st["evaluations"] == 1 + 6 * (st["steps"] + st["rejected"])
+
+    def chi(om):
+        conts = [O.Container(cfg["ff"], cfg["L"], t=t, tp=tp, mu=mu, T=T, Omega=om, lx=l[0],
+                             ly=l[1], channel=ch, kind=O.BUBBLE) for l in q for ch in (O.PP, O.PH)]
+        v, _, _, nc = O.integrate_batch(conts, rtol=1e-12, err_mode=O.ERR_GLOBAL, batch=4,
+                                        nthreads=8)
+        assert nc == 0
+        return v.reshape(len(q), 2, M, M)
+
+    dchi = chi(om1) - chi(om0)
+    dP, dC, dD = O.contract(dchi, *V)
+    for got, s0, ref in ((Pf, S0[0], dP), (Cf, S0[1], dC), (Df, S0[2], dD)):
+        scale = max(np.abs(ref).max(), np.abs(s0).max())
+        assert np.abs((got - s0) - ref).max() <= 5e-7 * scale
