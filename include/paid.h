@@ -105,6 +105,8 @@ typedef struct {
                            read-back of three counters, in three parts around
                            the evaluation launch) as HIP graphs and replay
                            them every round */
+  int eval_wg_per_cu;   /* workgroups of the region-evaluation launch per
+                           compute unit (0: 32) */
 } paid_config;
 
 /* one parameter row: dispersion, temperature and flow scale */

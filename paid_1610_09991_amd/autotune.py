@@ -3,8 +3,9 @@
 Times `paid_integrate` on a seeded sample of a workload for a grid of
 candidate settings and keeps the fastest: `batch` (the fewest leaves a
 container splits per round: the MaxTask analogue of Listing 2), `batch_max`
-(the most) and `max_active` (containers resident at once; 0 = as many as the
-region pool holds).  Every candidate must give the same answer within the
+(the most), `max_active` (containers resident at once; 0 = as many as the
+region pool holds) and `eval_wg_per_cu` (workgroups of the evaluation launch
+per compute unit).  Every candidate must give the same answer within the
 tolerance (checked against the first candidate's result), so the tuner only
 trades time.  The result is a small JSON profile:
 
@@ -34,8 +35,8 @@ def sample(cfg, fraction, seed=7):
     return cfg["params"], q[np.sort(rng.choice(len(q), k, replace=False))]
 
 
-def tune(workload="C2", fraction=0.25, batches=(4, 8, 16, 32), batch_maxes=(256, 1024, 4096),
-         actives=(0,), repeat=2, log=print):
+def tune(workload="C2", fraction=0.25, batches=(8, 32), batch_maxes=(1024, 4096, 16384),
+         actives=(0,), grids=(16, 32, 64), repeat=2, log=print):
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
     import paid_1610_09991_amd as P
@@ -49,10 +50,11 @@ def tune(workload="C2", fraction=0.25, batches=(4, 8, 16, 32), batch_maxes=(256,
     out = torch.empty((len(params), len(q), 2, M, M), dtype=torch.float64, device="cuda")
     ref = None
     results = []
-    for b, bm, act in itertools.product(batches, batch_maxes, actives):
+    for b, bm, act, g in itertools.product(batches, batch_maxes, actives, grids):
         if bm < b:
             continue
-        ctx = P.Context(stream=stream.cuda_stream, batch=b, batch_max=bm, max_active=act)
+        ctx = P.Context(stream=stream.cuda_stream, batch=b, batch_max=bm, max_active=act,
+                        eval_wg_per_cu=g, graph=1)
         best = None
         for _ in range(repeat):
             _, _, st, rc = ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=out)
@@ -62,16 +64,16 @@ def tune(workload="C2", fraction=0.25, batches=(4, 8, 16, 32), batch_maxes=(256,
             ref = val
         scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max(axis=(-1, -2), keepdims=True))
         dev = float(np.max(np.abs(val - ref) / scale)) / cfg["rtol"]
-        results.append({"batch": b, "batch_max": bm, "max_active": act, "seconds": best,
-                        "regions": st["regions"], "deviation_in_rtol": dev})
-        log(f"# batch {b:3d} batch_max {bm:5d} max_active {act}: {best:.4f} s, "
+        results.append({"batch": b, "batch_max": bm, "max_active": act, "eval_wg_per_cu": g,
+                        "seconds": best, "regions": st["regions"], "deviation_in_rtol": dev})
+        log(f"# batch {b:3d} batch_max {bm:5d} max_active {act} wg/CU {g:3d}: {best:.4f} s, "
             f"regions {st['regions']}, |delta| {dev:.2e} rtol")
         ctx.close()
     ok = [r for r in results if r["deviation_in_rtol"] <= 2.0]
     best = min(ok, key=lambda r: r["seconds"])
     return {"workload": workload, "sample": {"q": len(q), "params": len(params)},
             "config": {"batch": best["batch"], "batch_max": best["batch_max"],
-                       "max_active": best["max_active"]},
+                       "max_active": best["max_active"], "eval_wg_per_cu": best["eval_wg_per_cu"]},
             "results": results}
 
 

@@ -343,6 +343,8 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
   if (cfg.max_regions < 16 || cfg.max_regions > (1L << 28))
     return fail(nullptr, PAID_EINVAL, "max_regions must be in [16, 2^28]");
   if (!(cfg.nu >= 0)) return fail(nullptr, PAID_EINVAL, "nu must be >= 0");
+  if (cfg.eval_wg_per_cu < 0 || cfg.eval_wg_per_cu > 1024)
+    return fail(nullptr, PAID_EINVAL, "eval_wg_per_cu must be 0..1024");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev == 0) return fail(nullptr, PAID_EDEVICE, "no HIP device");
@@ -598,7 +600,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, cfg.device) == hipSuccess && v > 0)
       dev_cus = v;
   }
-  const int eval_grid = dev_cus * 16;
+  const int eval_grid = dev_cus * (cfg.eval_wg_per_cu > 0 ? cfg.eval_wg_per_cu : 32);
   long rounds = 0, eval_items = 0;
   double eval_ms = 0.0;
   // one device round in three parts: admission, roots, selection and work
