@@ -233,20 +233,35 @@ def test_invalid_arguments_are_rejected(ctx, P):
 
 
 def test_full_size_workload_sampled(P):
-    """The benchmark's workload at full size (23,040 containers, one call, the
-    benchmark's launch configuration), sampled containers against the oracle."""
+    """The benchmark's workload at full size (23,040 containers, one call) in
+    the benchmark's launch configuration (graph-replayed rounds, the shipped
+    launch profile), plain and with the shipped seed model; sampled
+    containers against the oracle."""
+    import json
+    import os
+    from paid_1610_09991_amd import seed_model as SM
     cfg = W.config("C2")
-    c = P.Context()
-    out, _, st, rc = c.integrate(cfg["params"], cfg["q"], cfg["ff"], cfg["L"], rtol=1e-6)
+    here = os.path.dirname(P.__file__)
+    with open(os.path.join(here, "tuned_c2.json")) as f:
+        tuned = json.load(f)["config"]
+    w, meta = SM.load()
+    c = P.Context(graph=1, **tuned)
+    runs = {}
+    for name, model in (("plain", None), ("seeded", w)):
+        c.set_seed_model(model, kappa=meta["kappa"])
+        out, _, st, rc = c.integrate(cfg["params"], cfg["q"], cfg["ff"], cfg["L"], rtol=1e-6)
+        assert rc == P.OK and st["not_converged"] == 0 and np.isfinite(out).all(), name
+        assert (st["seeded"] > 0) == (model is not None)
+        runs[name] = out
     c.close()
-    assert rc == P.OK and st["not_converged"] == 0 and np.isfinite(out).all()
     rng = np.random.default_rng(5)
     picks = [(ip, int(rng.integers(0, 576)), int(rng.integers(0, 2))) for ip in (0, 5, 9, 12, 14)]
     ref = oracle_refs(cfg, picks, 1e-9)
-    for k, (ip, iq, ch) in enumerate(picks):
-        assert gate_ratio(out[ip, iq, ch], ref[k], 1e-6) <= 1.0, (ip, iq, ch)
-    # symmetry of every output matrix
-    assert np.array_equal(out, np.swapaxes(out, -1, -2))
+    for name, out in runs.items():
+        for k, (ip, iq, ch) in enumerate(picks):
+            assert gate_ratio(out[ip, iq, ch], ref[k], 1e-6) <= 1.0, (name, ip, iq, ch)
+        # symmetry of every output matrix
+        assert np.array_equal(out, np.swapaxes(out, -1, -2))
 
 
 # ------------------------------------------------------------------ reduced precision
