@@ -1,0 +1,32 @@
+"""CPU checks of the benchmark's measurement constants."""
+import json
+import os
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_flop_count_per_item():
+    # integrand 289 x 80, separable projection for 9 form factors 13,176
+    assert bench.item_flops(9, 1, True) == 289 * 80 + 13176 == 36296
+    # dense Gram: 4 children x 2 M^2 (81 + 25)
+    assert bench.item_flops(25, 2, False) == 289 * 80 + 4 * 2 * 625 * 106
+
+
+def test_traffic_belongs_to_the_profiled_kernel():
+    """The HBM bytes per item come from counters taken with one version of
+    the kernel; if its sources change, the counters must be taken again and
+    the hash and figure in bench.py updated (the benchmark otherwise reports
+    null traffic)."""
+    assert bench.kernel_sources_sha256() == bench.TRAFFIC_SOURCES_SHA256
+    with open(os.path.join(ROOT, "profiles", "k_children_c2_counters.md")) as f:
+        txt = f.read()
+    assert f"per work item {bench.TRAFFIC_BYTES_PER_ITEM} B" in txt
+
+
+def test_shipped_launch_profile_is_complete():
+    with open(os.path.join(ROOT, "paid_1610_09991_amd", "tuned_c2.json")) as f:
+        cfg = json.load(f)["config"]
+    assert set(cfg) == {"batch", "batch_max", "max_active", "eval_wg_per_cu"}
+    assert 1 <= cfg["batch"] <= cfg["batch_max"]
