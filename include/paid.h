@@ -66,8 +66,13 @@ enum {
   PAID_ERR_GLOBAL = 0,       /* sum over pairs and leaves of |Q_N - Q_2N| <=
                                 max(atol, rtol * sum over pairs |value|)  (the
                                 paper's global criterion) */
-  PAID_ERR_PER_INTEGRAL = 1  /* every pair: sum over leaves of its error <=
+  PAID_ERR_PER_INTEGRAL = 1, /* every pair: sum over leaves of its error <=
                                 max(atol, rtol * max(|value_pq|, nu max |value|)) */
+  PAID_ERR_WEIGHTED = 2      /* the global test with pair weights w (set with
+                                paid_set_pair_weights): sum over leaves and pairs
+                                of w |Q_N - Q_2N| <= max(atol, rtol * sum w |value|);
+                                with w from the couplings (Eq. P_globerr) it
+                                bounds the error of the contracted matrices */
 };
 
 /* arithmetic of the form-factor projection */
@@ -219,6 +224,14 @@ int paid_set_seed_model(struct paid_ctx *ctx, const float *weights, int dmax, do
  * converged tree in the model frame [n_ctr][256] (FP32).  Both pointers are
  * caller-owned, sized for each call, host or device; NULLs turn it off. */
 int paid_set_label_output(struct paid_ctx *ctx, float *features, float *labels);
+
+/* Pair weights of PAID_ERR_WEIGHTED for every later paid_integrate call:
+ * w [n_ctr][n_ff][n_ff] (FP64, >= 0, containers in the order of out), the
+ * weights of the full matrix entries; the stored pair p < q carries
+ * w_pq + w_qp and the pair p = p carries w_pp (so that, for dX = V chi V and
+ * w_pq = (sum_m |V_mp|)(sum_n |V_qn|), sum_mn |dX_mn| <= sum w |d chi|).
+ * Host or device pointer, caller-owned and sized for each call; NULL clears. */
+int paid_set_pair_weights(struct paid_ctx *ctx, const double *w);
 
 /* Model forward pass: x [n][7] -> y [n][256]. */
 int paid_mlp_forward(struct paid_ctx *ctx, const float *w, const float *x, int n, float *y);

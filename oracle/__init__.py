@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 BUBBLE_DOT, BUBBLE, UNIT, GAUSS = 0, 1, 2, 3
 PP, PH = 0, 1
 MODE_A, MODE_B = 0, 1
-ERR_GLOBAL, ERR_PER_INTEGRAL = 0, 1
+ERR_GLOBAL, ERR_PER_INTEGRAL, ERR_WEIGHTED = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -43,7 +43,8 @@ class Problem(C.Structure):
                 ("T", C.c_double), ("Omega", C.c_double),
                 ("lx", C.c_double), ("ly", C.c_double),
                 ("ff_L", C.c_int), ("n_ff", C.c_int), ("ff", C.POINTER(C.c_double)),
-                ("gx", C.c_double), ("gy", C.c_double), ("gsigma", C.c_double)]
+                ("gx", C.c_double), ("gy", C.c_double), ("gsigma", C.c_double),
+                ("pair_w", C.POINTER(C.c_double))]
 
 
 class Options(C.Structure):
@@ -142,14 +143,18 @@ class Container:
     """One adaptive problem: (parameters, scale, transfer momentum, channel)."""
 
     def __init__(self, ff, ff_L, *, t=1.0, tp=0.0, mu=0.0, T=0.1, Omega=0.1, lx=0.0, ly=0.0,
-                 channel=PH, kind=BUBBLE_DOT, gauss=(0.0, 0.0, 1.0)):
+                 channel=PH, kind=BUBBLE_DOT, gauss=(0.0, 0.0, 1.0), pair_w=None):
         self.ff = np.ascontiguousarray(ff, dtype=np.float64)
         nb = (2 * ff_L + 1) ** 2
         if self.ff.ndim != 2 or self.ff.shape[1] != nb:
             raise ValueError("ff must be [n_ff][(2L+1)^2]")
         self.M = self.ff.shape[0]
+        self.pair_w = None if pair_w is None else np.ascontiguousarray(pair_w, dtype=np.float64)
+        if self.pair_w is not None and self.pair_w.shape != (self.M, self.M):
+            raise ValueError("pair_w must be [n_ff][n_ff]")
         self.s = Problem(kind, channel, t, tp, mu, T, Omega, lx, ly, ff_L, self.M,
-                         _dp(self.ff), gauss[0], gauss[1], gauss[2])
+                         _dp(self.ff), gauss[0], gauss[1], gauss[2],
+                         _dp(self.pair_w) if self.pair_w is not None else None)
 
     def integrand(self, px, py) -> float:
         return lib().po_integrand(C.byref(self.s), float(px), float(py))
@@ -286,3 +291,10 @@ def contract(chi, VP, VC, VD):
     dC = -(VC @ ph @ VC)
     dD = 2.0 * (VD @ ph @ VD) - VC @ ph @ VD - VD @ ph @ VC
     return dP, dC, dD
+
+
+def weights_from_couplings(V):
+    """Weights of the full matrix entries for which sum_mn |dX_mn| <=
+    sum_pq w_pq |d chi_pq| with dX = V chi V: w_pq = (sum_m |V_mp|)(sum_n |V_qn|)."""
+    A = np.abs(np.asarray(V, dtype=np.float64))
+    return np.outer(A.sum(axis=0), A.sum(axis=1))

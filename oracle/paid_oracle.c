@@ -443,23 +443,26 @@ static void po_store_free(po_store *s) {
 /* tolerance per pair from the current values (Sec. 3 global criterion read
  * as relative to the values; the per-integral variant floors small entries
  * at nu times the largest one). */
-static void po_tolerances(const po_options *o, int MU, const double *val, double *tau,
-                          double *eps_global) {
+static void po_tolerances(const po_options *o, int MU, const double *val, const double *w,
+                          double *tau, double *eps_global) {
   double vmax = 0.0, l1 = 0.0;
   for (int k = 0; k < MU; ++k) {
     vmax = fmax(vmax, fabs(val[k]));
-    l1 += fabs(val[k]);
+    l1 += (o->err_mode == PO_ERR_WEIGHTED ? w[k] : 1.0) * fabs(val[k]);
   }
   for (int k = 0; k < MU; ++k)
     tau[k] = fmax(o->atol, o->rtol * fmax(fabs(val[k]), o->nu * vmax));
   *eps_global = fmax(o->atol, o->rtol * l1);
 }
 
-static int po_converged(const po_options *o, int MU, const double *ERR, const double *tau,
-                        double eps_global) {
-  if (o->err_mode == PO_ERR_GLOBAL) {
+/* Global criterion (Sec. 3): sum over pairs of the error against eps; with
+ * pair weights (Eq. P_globerr: the error of the contracted matrix is
+ * bounded by the couplings times the pair errors) the sum is weighted. */
+static int po_converged(const po_options *o, int MU, const double *ERR, const double *w,
+                        const double *tau, double eps_global) {
+  if (o->err_mode == PO_ERR_GLOBAL || o->err_mode == PO_ERR_WEIGHTED) {
     double s = 0.0;
-    for (int k = 0; k < MU; ++k) s += ERR[k];
+    for (int k = 0; k < MU; ++k) s += (o->err_mode == PO_ERR_WEIGHTED ? w[k] : 1.0) * ERR[k];
     return s <= eps_global;
   }
   for (int k = 0; k < MU; ++k)
@@ -498,7 +501,7 @@ static double po_key(const po_options *o, int np, int pair, const double *err,
   double k = 0.0;
   for (int j = 0; j < np; ++j) {
     int pj = (pair < 0) ? j : pair;
-    k += (o->err_mode == PO_ERR_GLOBAL) ? err[j] : err[j] * inv_tau[pj];
+    k += (o->err_mode == PO_ERR_GLOBAL) ? err[j] : err[j] * inv_tau[pj];  /* 1/tau or w */
   }
   return k;
 }
@@ -536,12 +539,20 @@ static int po_integrate_impl(const po_problem *pr, const po_options *o, double *
   double *ERR = (double *)calloc(MU, sizeof(double));
   double *tau = (double *)calloc(MU, sizeof(double));
   double *itau = (double *)calloc(MU, sizeof(double));
+  double *pw = (double *)calloc(MU, sizeof(double)); /* pair weights (weighted mode) */
   double *qn = (double *)calloc(MU, sizeof(double));
   long *pick = (long *)calloc(o->batch, sizeof(long));
   po_stats S;
   memset(&S, 0, sizeof S);
   int rc = -3;
-  if (!val || !ERR || !tau || !itau || !qn || !pick) goto done;
+  if (!val || !ERR || !tau || !itau || !pw || !qn || !pick) goto done;
+  if (o->err_mode == PO_ERR_WEIGHTED) {
+    if (!pr->pair_w) goto done;
+    int k = 0;
+    for (int p = 0; p < M; ++p)
+      for (int q = p; q < M; ++q, ++k)
+        pw[k] = (p == q) ? pr->pair_w[p * M + p] : pr->pair_w[p * M + q] + pr->pair_w[q * M + p];
+  }
 
   /* Listing 1: root task(s) on the whole zone */
   {
@@ -559,8 +570,8 @@ static int po_integrate_impl(const po_problem *pr, const po_options *o, double *
     }
     po_resum(&s, o->mode, MU, val, ERR);
     double eg;
-    po_tolerances(o, MU, val, tau, &eg);
-    for (int k = 0; k < MU; ++k) itau[k] = 1.0 / tau[k];
+    po_tolerances(o, MU, val, pw, tau, &eg);
+    for (int k = 0; k < MU; ++k) itau[k] = (o->err_mode == PO_ERR_WEIGHTED) ? pw[k] : 1.0 / tau[k];
     for (long id = 0; id < s.n; ++id)
       if (po_heap_push(&h, po_key(o, s.np, s.pair[id], &s.err[id * s.np], itau), id) != 0)
         goto done;
@@ -570,11 +581,11 @@ static int po_integrate_impl(const po_problem *pr, const po_options *o, double *
     /* termination test (master thread in Listing 5), with an exact re-sum
        from the leaves before it is accepted */
     double eg;
-    po_tolerances(o, MU, val, tau, &eg);
-    if (po_converged(o, MU, ERR, tau, eg)) {
+    po_tolerances(o, MU, val, pw, tau, &eg);
+    if (po_converged(o, MU, ERR, pw, tau, eg)) {
       po_resum(&s, o->mode, MU, val, ERR);
-      po_tolerances(o, MU, val, tau, &eg);
-      if (po_converged(o, MU, ERR, tau, eg)) {
+      po_tolerances(o, MU, val, pw, tau, &eg);
+      if (po_converged(o, MU, ERR, pw, tau, eg)) {
         S.converged = 1;
         break;
       }
@@ -582,7 +593,8 @@ static int po_integrate_impl(const po_problem *pr, const po_options *o, double *
     if (h.n == 0) break;
     long leaves = h.n;
     if (leaves + 3 > o->max_regions) break;
-    for (int k = 0; k < MU; ++k) itau[k] = 1.0 / tau[k];
+    if (o->err_mode == PO_ERR_PER_INTEGRAL)
+      for (int k = 0; k < MU; ++k) itau[k] = 1.0 / tau[k];
     /* Listing 2: extract up to MaxTask tasks of largest error */
     int nb = 0;
     while (nb < o->batch && h.n > 0 && leaves + 3 * (nb + 1) <= o->max_regions)
@@ -651,6 +663,7 @@ done:
   free(ERR);
   free(tau);
   free(itau);
+  free(pw);
   free(qn);
   free(pick);
   free(h.a);

@@ -39,7 +39,8 @@ enum { PO_PP = 0, PO_PH = 1 };
 enum { PO_MODE_A = 0,  /* one task = (region, form-factor pair), paper-literal */
        PO_MODE_B = 1 };/* one task = region, all pairs refined together (shared tree) */
 /* termination */
-enum { PO_ERR_GLOBAL = 0, PO_ERR_PER_INTEGRAL = 1 };
+enum { PO_ERR_GLOBAL = 0, PO_ERR_PER_INTEGRAL = 1,
+       PO_ERR_WEIGHTED = 2 };  /* global criterion with pair weights (Eq. P_globerr) */
 
 typedef struct {
   int kind, channel;
@@ -49,6 +50,9 @@ typedef struct {
   int n_ff;                     /* number of form factors M */
   const double *ff;             /* [n_ff][(2L+1)^2] coefficients over the box basis */
   double gx, gy, gsigma;        /* PO_GAUSS centre and width */
+  const double *pair_w;         /* PO_ERR_WEIGHTED: [n_ff][n_ff] weights of the full
+                                   matrix entries; the stored pair p < q carries
+                                   w_pq + w_qp, the pair p = p carries w_pp */
 } po_problem;
 
 typedef struct {

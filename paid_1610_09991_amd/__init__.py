@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpaid.so")
 OK, ENOCONV, EINVAL, ENOMEM, EDEVICE, EINTERNAL = 0, 1, -1, -2, -3, -4
 BUBBLE_DOT, BUBBLE, UNIT, GAUSS = 0, 1, 2, 3
 PP, PH = 1, 2
-ERR_GLOBAL, ERR_PER_INTEGRAL = 0, 1
+ERR_GLOBAL, ERR_PER_INTEGRAL, ERR_WEIGHTED = 0, 1, 2
 FP64, FP32, BF16X3 = 0, 1, 2
 GRAM_MFMA, GRAM_SEPARABLE = 0, 1
 
@@ -82,7 +82,7 @@ EXPORTS = ("paid_config_default", "paid_create", "paid_integrate", "paid_kernel_
            "paid_children_eval", "paid_destroy", "paid_last_error", "paid_mlp_nparams",
            "paid_set_seed_model", "paid_set_label_output", "paid_mlp_forward",
            "paid_mlp_loss_grad", "paid_mlp_adam", "paid_train_opts_default", "paid_seed_train",
-           "paid_contract", "paid_flow_opts_default", "paid_flow")
+           "paid_contract", "paid_flow_opts_default", "paid_flow", "paid_set_pair_weights")
 
 _lib = None
 
@@ -117,6 +117,7 @@ def lib():
         L.paid_mlp_nparams.restype = C.c_long
         L.paid_set_seed_model.argtypes = [vp, vp, C.c_int, C.c_double]
         L.paid_set_label_output.argtypes = [vp, vp, vp]
+        L.paid_set_pair_weights.argtypes = [vp, vp]
         L.paid_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
         L.paid_mlp_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int, vp, dp]
         L.paid_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float]
@@ -245,6 +246,13 @@ class Context:
             return
         w = weights if hasattr(weights, "data_ptr") else np.ascontiguousarray(weights, np.float32)
         self._check(lib().paid_set_seed_model(self.h, _ptr(w), dmax, kappa), allow_noconv=False)
+
+    def set_pair_weights(self, w):
+        """Pair weights [n_ctr][M][M] of the weighted error mode (kept alive
+        here; None clears)."""
+        self._pw = None if w is None else (w if hasattr(w, "data_ptr") else _f64(w))
+        self._check(lib().paid_set_pair_weights(self.h, _ptr(self._pw) if w is not None else None),
+                    allow_noconv=False)
 
     def set_label_output(self, features=None, labels=None):
         """Arm per-container features [n][7] and tree labels [n][256] (FP32

@@ -60,6 +60,8 @@ struct paid_ctx {
   int seed_dmax = 8;
   double seed_kappa = 2.0;
   float *feat_out = nullptr, *lab_out = nullptr;
+  const double *pair_w = nullptr;  // weighted mode: caller's [n_ctr][M][M]
+  DevBuf pairw;
   int *host_counters = nullptr;  // pinned
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profile: around the evaluation launch
 };
@@ -330,7 +332,8 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
   if (cfg.N != 4) return fail(nullptr, PAID_EINVAL, "only N = 4 is implemented");
   if (cfg.batch < 1 || cfg.batch_max < cfg.batch)
     return fail(nullptr, PAID_EINVAL, "need 1 <= batch <= batch_max");
-  if (cfg.err_mode != PAID_ERR_GLOBAL && cfg.err_mode != PAID_ERR_PER_INTEGRAL)
+  if (cfg.err_mode != PAID_ERR_GLOBAL && cfg.err_mode != PAID_ERR_PER_INTEGRAL &&
+      cfg.err_mode != PAID_ERR_WEIGHTED)
     return fail(nullptr, PAID_EINVAL, "bad err_mode");
   if (cfg.precision != PAID_FP64 && cfg.precision != PAID_FP32 && cfg.precision != PAID_BF16X3)
     return fail(nullptr, PAID_EINVAL, "bad precision");
@@ -393,7 +396,7 @@ void paid_destroy(paid_ctx *c) {
                     &c->slot_d,  &c->sel,  &c->dv,    &c->de,    &c->dep,   &c->itau,
                     &c->errp,    &c->stl,  &c->counters, &c->outs, &c->errs,
                     &c->seedw,   &c->sfeat, &c->sfold, &c->sy,  &c->sact,  &c->pyr,
-                    &c->seedd,   &c->ifill, &c->labtmp};
+                    &c->seedd,   &c->ifill, &c->labtmp, &c->pairw};
   for (DevBuf *b : bufs) b->release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -548,6 +551,19 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   HIPCHK(c, hipMemsetAsync(c->slot_i.p, 0, sizeof(int) * (8 * W + 8), c->stream));
   HIPCHK(c, hipMemsetAsync(c->counters.p, 0, 256, c->stream));
   HIPCHK(c, hipMemsetAsync(c->stl.p, 0, sizeof(long) * 3 * W, c->stream));
+
+  if (cfg.err_mode == PAID_ERR_WEIGHTED) {
+    if (!c->pair_w) return fail(c, PAID_EINVAL, "PAID_ERR_WEIGHTED needs paid_set_pair_weights");
+    const size_t nw = (size_t)n_ctr * M * M;
+    const double *dw;
+    int rw;
+    if ((rw = stage_in(c, c->pair_w, nw, c->pairw, dw)) != PAID_OK) return rw;
+    std::vector<double> hw;
+    if ((rw = to_host(c, c->pair_w, nw, hw)) != PAID_OK) return rw;
+    for (size_t i = 0; i < nw; ++i)
+      if (!(hw[i] >= 0.0) || !std::isfinite(hw[i])) return fail(c, PAID_EINVAL, "pair weight %zu not finite and >= 0", i);
+    P.pair_w = dw;
+  }
 
   // learned seeding: model features of every container, then the model
   const bool want_labels = c->lab_out != nullptr || c->feat_out != nullptr;
@@ -888,6 +904,13 @@ int paid_set_seed_model(paid_ctx *c, const float *w, int dmax, double kappa) {
       return fail(c, PAID_EINVAL, "model weight %ld is not finite", i);
     }
   c->seed_on = true;
+  return PAID_OK;
+}
+
+int paid_set_pair_weights(paid_ctx *c, const double *w) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  c->pair_w = w;
   return PAID_OK;
 }
 

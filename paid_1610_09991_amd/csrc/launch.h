@@ -89,6 +89,8 @@ struct Problem {      // everything the round kernels need, passed by value
   int *ifill;                 // [W*bmax] 1 if the work item evaluated its node grid
   // tree labels of finished containers (model frame), NULL = off
   float *labels;              // [n_ctr][256]
+  // pair weights of the weighted global test (err_mode 2)
+  const double *pair_w;       // [n_ctr][M][M] full-matrix weights
 };
 
 constexpr int kSeedG = 16;                    // cells per axis of the density grid

@@ -156,6 +156,15 @@ __device__ int tolerance_test(const Problem &P, int s, double *shd, double &eps,
     deficit = E - eps;
     return E <= eps;
   }
+  if (P.err_mode == 2) {  // weighted sums (the keys carry the same weights)
+    double aw = 0.0;
+    for (int pid = t; pid < P.MU; pid += blockDim.x)
+      aw += (double)P.itau[(long)s * P.MU + pid] * fabs(P.val[(long)s * P.MU + pid]);
+    eps = fmax(P.atol, P.rtol * block_sum(aw, shd));
+    double E = P.err[s];
+    deficit = E - eps;
+    return E <= eps;
+  }
   // per integral: every pair within its own tolerance; deficit in tau units
   double ex = 0.0;
   int bad = 0;
@@ -288,8 +297,8 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     unsigned long long sex = sinc - s8;
     double dd = deficit * scale;
     unsigned long long dfix = dd >= 4.0e18 ? 4000000000000000000ull : (unsigned long long)(dd > 0 ? dd : 0.0);
-    int beps = (P.err_mode == 0) ? key_bin(eps, eb) : 0;
-    if (P.err_mode == 0 && eps >= maxkey) beps = -1;  // no single leaf exceeds eps
+    int beps = (P.err_mode != 1) ? key_bin(eps, eb) : 0;
+    if (P.err_mode != 1 && eps >= maxkey) beps = -1;  // no single leaf exceeds eps
     // first bin b (in this lane's 8) meeting all conditions
     int found = kBins, fcnt = 0;
     unsigned int cc = cex;

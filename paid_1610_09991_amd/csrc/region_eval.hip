@@ -471,7 +471,7 @@ __device__ double store_region(WaveLds<L> &S, const Problem &P, int s, long ri, 
     double q = S.cq[pid], e = fabs(S.ce[pid]);
     P.Q[base * P.MU + pid] = q;
     if (P.E) P.E[base * P.MU + pid] = (float)e;
-    part += (P.err_mode == 1) ? e * (double)P.itau[(long)s * P.MU + pid] : e;
+    part += (P.err_mode != 0) ? e * (double)P.itau[(long)s * P.MU + pid] : e;
   }
   double key = wave_sum(part);
   if (lane == 0) {
@@ -599,8 +599,20 @@ __global__ void __launch_bounds__(64) k_root(Problem P) {
   if (s >= P.W || P.state[s] != SLOT_NEW) return;
   build_pidmap<L>(pidmap, threadIdx.x, 64);
   const int c = P.cid[s];
-  // key weights for the per-integral mode start at one
-  for (int pid = threadIdx.x; pid < P.MU; pid += 64) P.itau[(long)s * P.MU + pid] = 1.0f;
+  // key weights: the pair weights in the weighted mode, else one (the
+  // per-integral mode refreshes them with 1/tau every round)
+  for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
+    float w = 1.0f;
+    if (P.err_mode == 2) {
+      const int M = P.M;
+      int p = 0, k = pid;
+      while (k >= M - p) { k -= M - p; ++p; }
+      const int q = p + k;
+      const double *W = P.pair_w + (long)c * M * M;
+      w = (float)((p == q) ? W[p * M + p] : W[p * M + q] + W[q * M + p]);
+    }
+    P.itau[(long)s * P.MU + pid] = w;
+  }
   __syncthreads();
   int D = 0;
   bool placeholder = false;

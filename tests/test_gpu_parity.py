@@ -327,3 +327,55 @@ def test_graph_replayed_rounds_match_eager_rounds(P):
             for k in ("regions", "splits", "kernel_evals", "rounds", "launch_rounds"):
                 assert sgot[k] == sref[k], (rep, k)
             eager.integrate(cfg["params"], cfg["q"][:5], cfg["ff"], cfg["L"], rtol=1e-4)
+
+
+# ------------------------------------------------------------------ weighted global test
+def test_weighted_mode_with_unit_pair_weights_is_the_global_mode(P):
+    cfg = W.config("C1")
+    n = len(cfg["q"]) * 2
+    Wm = np.broadcast_to(np.full((5, 5), 0.5) + 0.5 * np.eye(5), (n, 5, 5)).copy()
+    args = (cfg["params"], cfg["q"], cfg["ff"], cfg["L"])
+    with P.Context(max_regions=1 << 14, max_active=64) as g, \
+            P.Context(max_regions=1 << 14, max_active=64, err_mode=P.ERR_WEIGHTED) as w:
+        a, _, sa, _ = g.integrate(*args, rtol=1e-6)
+        w.set_pair_weights(Wm)
+        b, _, sb, _ = w.integrate(*args, rtol=1e-6)
+    assert np.array_equal(a, b) and sa["regions"] == sb["regions"]
+
+
+def test_weighted_mode_bounds_the_contracted_error(P):
+    """weights from random couplings per container (Eq. P_globerr read as a
+    bound of the contracted matrices' summed error): the weighted error of
+    every container against the oracle stays within rtol of its weighted sum"""
+    cfg = W.config("C1")
+    q = cfg["q"][[2, 19, 33, 50]]
+    p = cfg["params"][0]
+    rng = np.random.default_rng(12)
+    Ws = np.stack([O.weights_from_couplings(rng.normal(size=(5, 5))) for _ in range(len(q) * 2)])
+    with P.Context(max_regions=1 << 15, max_active=16, err_mode=P.ERR_WEIGHTED) as w:
+        w.set_pair_weights(Ws)
+        out, _, st, rc = w.integrate(cfg["params"], q, cfg["ff"], cfg["L"], rtol=1e-6)
+    assert rc == 0
+    conts = [O.Container(cfg["ff"], cfg["L"], t=p[0], tp=p[1], mu=p[2], T=p[3], Omega=p[4],
+                         lx=l[0], ly=l[1], channel=ch) for l in q for ch in (O.PP, O.PH)]
+    ref, _, _, nc = O.integrate_batch(conts, rtol=1e-10, err_mode=O.ERR_GLOBAL, batch=4,
+                                      nthreads=THREADS)
+    assert nc == 0
+    gpu = out.reshape(-1, 5, 5)
+    iu = np.triu_indices(5)
+    for k in range(len(conts)):
+        pw = np.where(np.eye(5) > 0, Ws[k], Ws[k] + Ws[k].T)[iu]
+        err = np.sum(pw * np.abs(gpu[k][iu] - ref[k][iu]))
+        assert err <= 1e-6 * np.sum(pw * np.abs(ref[k][iu])), k
+
+
+def test_weighted_mode_argument_checks(P):
+    cfg = W.config("C1")
+    with P.Context(err_mode=P.ERR_WEIGHTED) as w:
+        with pytest.raises(P.PaidError):  # no weights set
+            w.integrate(cfg["params"], cfg["q"][:1], cfg["ff"], cfg["L"], rtol=1e-4)
+        bad = np.ones((2, 5, 5))
+        bad[1, 2, 3] = -1.0
+        w.set_pair_weights(bad)
+        with pytest.raises(P.PaidError):
+            w.integrate(cfg["params"], cfg["q"][:1], cfg["ff"], cfg["L"], rtol=1e-4)

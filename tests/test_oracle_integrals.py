@@ -189,3 +189,42 @@ def test_per_integral_mode_meets_each_tolerance():
     tau = rtol * np.maximum(np.abs(v), nu * np.abs(v).max())
     assert (e <= tau * (1 + 1e-12)).all()
     assert (np.abs(v - ref) <= tau).all()
+
+
+# ------------------------------------------------------------------ weighted global criterion
+def _wcont(pair_w, **kw):
+    ff = W.ff5()
+    return O.Container(ff, 1, t=1.0, tp=-0.2, mu=-0.4, T=0.1, Omega=0.3, lx=1.1, ly=0.4,
+                       channel=O.PH, pair_w=pair_w, **kw)
+
+
+def test_weighted_criterion_with_unit_pair_weights_is_the_global_one():
+    """pair weights 1 (w_pp = 1, w_pq = w_qp = 1/2) reproduce the global mode bit for bit"""
+    Wm = np.full((5, 5), 0.5) + 0.5 * np.eye(5)
+    v1, e1, s1 = _wcont(Wm).integrate(rtol=1e-6, err_mode=O.ERR_WEIGHTED, batch=4)
+    v0, e0, s0 = _wcont(None).integrate(rtol=1e-6, err_mode=O.ERR_GLOBAL, batch=4)
+    assert np.array_equal(v1, v0) and np.array_equal(e1, e0)
+    assert s1["regions"] == s0["regions"]
+
+
+def test_weighted_criterion_is_scale_invariant():
+    rng = np.random.default_rng(8)
+    Wm = O.weights_from_couplings(rng.normal(size=(5, 5)))
+    a = _wcont(Wm).integrate(rtol=1e-6, err_mode=O.ERR_WEIGHTED, batch=4)
+    b = _wcont(4.0 * Wm).integrate(rtol=1e-6, err_mode=O.ERR_WEIGHTED, batch=4)
+    assert np.array_equal(a[0], b[0]) and a[2]["regions"] == b[2]["regions"]
+
+
+def test_weighted_criterion_holds_against_a_tight_reference():
+    """the weighted error of the result stays within rtol of the weighted sum;
+    a weight on one entry alone refines for that integral only"""
+    rng = np.random.default_rng(9)
+    ref, _, _ = _wcont(None).integrate(rtol=1e-11, err_mode=O.ERR_GLOBAL, batch=8)
+    iu = np.triu_indices(5)
+    for Wm in (O.weights_from_couplings(rng.normal(size=(5, 5))), np.eye(5)[:, :1] @ np.eye(5)[:1, :]):
+        pw = np.where(np.eye(5) > 0, Wm, Wm + Wm.T)[iu]
+        v, _, st = _wcont(Wm).integrate(rtol=1e-6, err_mode=O.ERR_WEIGHTED, batch=4)
+        err = np.sum(pw * np.abs(v[iu] - ref[iu]))
+        assert err <= 1e-6 * np.sum(pw * np.abs(ref[iu]))
+    _, _, sg = _wcont(None).integrate(rtol=1e-6, err_mode=O.ERR_GLOBAL, batch=4)
+    assert st["regions"] < sg["regions"]
