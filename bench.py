@@ -46,8 +46,8 @@ K_FLOPS_PER_NODE = 80
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2410
-TRAFFIC_SOURCES_SHA256 = "7d243ae5680038c4e5c284442b5a93e46e258deb9d969a2fcacca1249a57a845"
+TRAFFIC_BYTES_PER_ITEM = 2404
+TRAFFIC_SOURCES_SHA256 = "d71fcb245e121a137121265179c8497dc623d3d125b01bd0414ca118b26a1c2c"
 
 
 def kernel_sources_sha256() -> str:
