@@ -63,6 +63,8 @@ struct paid_ctx {
   const double *pair_w = nullptr;  // weighted mode: caller's [n_ctr][M][M]
   DevBuf pairw;
   int *host_counters = nullptr;  // pinned
+  int max_J = 1;                 // rows of the largest table of the last build
+  int lds_limit = 0;             // LDS bytes per workgroup (device attribute)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profile: around the evaluation launch
 };
 
@@ -179,6 +181,18 @@ Entry make_entry(const paid_params &p, int kind, int &off) {
   return e;
 }
 
+// LDS bytes one workgroup may use on the context's device (queried once)
+int lds_limit(paid_ctx *c) {
+  if (c->lds_limit <= 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->cfg.device) != hipSuccess ||
+        v <= 0)
+      v = 65536;
+    c->lds_limit = v;
+  }
+  return c->lds_limit;
+}
+
 int build_tables(paid_ctx *c, const paid_params *params, int n, int kind) {
   std::vector<Entry> es(n);
   int off = 0, maxJ = 1;
@@ -197,6 +211,7 @@ int build_tables(paid_ctx *c, const paid_params *params, int n, int kind) {
   a.entries = c->entries.as<Entry>();
   a.n_entries = n;
   a.max_J = maxJ;
+  c->max_J = maxJ;
   a.tab = c->tab.as<double>();
   a.zeta = c->zeta.as<double>();
   a.svals = c->svals.as<double2>();
@@ -494,6 +509,8 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   memset(&P, 0, sizeof P);
   P.entries = c->entries.as<Entry>();
   P.tab = c->tab.as<double>();
+  P.tab_rows = c->max_J;
+  P.lds_limit = lds_limit(c);
   P.ctr = c->ctr.as<Ctr>();
   P.n_ctr = n_ctr;
   P.kind = cfg.kind;
@@ -512,6 +529,9 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   P.M = M;
   P.MU = MU;
   P.ff_identity = identity;
+  if (eval_lds_bytes(P) == 0)
+    return fail(c, PAID_EINVAL, "frequency-sum table of %d rows does not fit in LDS (T too small against the band)",
+                P.tab_rows);
   P.ffc = c->ffc.as<double>();
   P.W = (int)W;
   P.cap = cap;
@@ -823,6 +843,8 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
   memset(&P, 0, sizeof P);
   P.entries = c->entries.as<Entry>();
   P.tab = c->tab.as<double>();
+  P.tab_rows = c->max_J;
+  P.lds_limit = lds_limit(c);
   P.ctr = c->ctr.as<Ctr>();
   P.n_ctr = 1;
   P.kind = cfg.kind;
@@ -838,6 +860,9 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
   P.M = M;
   P.MU = MU;
   P.ff_identity = identity;
+  if (eval_lds_bytes(P) == 0)
+    return fail(c, PAID_EINVAL, "frequency-sum table of %d rows does not fit in LDS (T too small against the band)",
+                P.tab_rows);
   P.ffc = c->ffc.as<double>();
   P.W = 1;
   P.cap = cap;

@@ -55,6 +55,8 @@ struct Problem {      // everything the round kernels need, passed by value
   long cap;                   // regions per slot
   int bmin, bmax;
   int lds_wave_doubles;       // per-wave LDS of the evaluation kernel (set at launch)
+  int tab_rows;               // rows of the largest frequency-sum table (the LDS table)
+  int lds_limit;              // bytes of LDS a workgroup may use on the device
   uint64_t *code;             // [W*cap]
   double *key;                // [W*cap]
   double *Q;                  // [W*cap*MU]
@@ -134,6 +136,8 @@ hipError_t launch_admit(const Problem &p, hipStream_t s);
 hipError_t launch_root(const Problem &p, hipStream_t s);
 hipError_t launch_select(const Problem &p, hipStream_t s);
 hipError_t launch_worklist(const Problem &p, hipStream_t s);
+// dynamic LDS bytes of the evaluation kernel for p (0: the table does not fit)
+size_t eval_lds_bytes(const Problem &p);
 hipError_t launch_eval(const Problem &p, int grid, hipStream_t s);
 hipError_t launch_update(const Problem &p, hipStream_t s);
 hipError_t launch_finalize(const Problem &p, hipStream_t s);

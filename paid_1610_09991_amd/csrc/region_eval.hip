@@ -35,7 +35,6 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwoPi = 6.28318530717958647692;
 constexpr double kSqrt2 = 1.41421356237309504880;
-constexpr int kTabRowsLds = 96;  // table rows a workgroup holds in LDS
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -47,18 +46,31 @@ struct Dims {
   static constexpr int MU = MB * (MB + 1) / 2;  // pairs of box functions
 };
 
-// per-wave scratch in LDS
+// per-wave scratch in LDS.  Buffers of different phases share storage: the
+// integrand g is dead once the y-sums are formed (separable path), the
+// per-axis cosines once g is, and the separable path never uses the box
+// harmonics of the dense Gram.
 template <int L>
 struct WaveLds {
   static constexpr int NB = Dims<L>::NB, MB = Dims<L>::MB, NP = Dims<L>::NP, MU = Dims<L>::MU;
-  double g[kNX * kNX];             // integrand at the shared nodes
-  double cp[2][kNX], cm[2][kNX];   // cos(l/2 + p), cos(l/2 - p) per axis
-  double u[2][kNX][NB];            // box harmonics per axis
-  double pp[2][kNX][NP];           // their products u_a u_c per axis
-  double pos[2][kNX];              // coordinates
-  double h2[2][kNX][NP];           // y-sums with the fine weights, per child row
-  double h1[2][kNCo * 2 - 1][NP];  // y-sums with the coarse weights (even x)
-  double g2[NP * NP], g1[NP * NP]; // x-sums of one child
+  double pp[2][kNX][NP];           // products u_a u_c of the box harmonics per axis
+  union {
+    double g[kNX * kNX];           // integrand at the shared nodes
+    struct {
+      double g2[NP * NP], g1[NP * NP];  // x-sums of one child (separable path)
+    };
+  };
+  union {
+    struct {
+      double cp[2][kNX], cm[2][kNX];    // cos(l/2 + p), cos(l/2 - p) per axis
+      double pos[2][kNX];               // coordinates
+    };
+    double h1[2][kNCo * 2 - 1][NP];     // y-sums with the coarse weights (even x)
+  };
+  union {
+    double h2[2][kNX][NP];         // y-sums with the fine weights, per child row
+    double u[2][kNX][NB];          // box harmonics per axis (dense Gram)
+  };
   double cq[MU], ce[MU];           // one child's Q_2N and E over form-factor pairs
   // general form-factor sets only (dropped from the allocation otherwise)
   double tq[MB * MB], ts[MB * MB], tr[MB * MB];
@@ -745,60 +757,88 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int 
   }
 }
 
+// parameter row of slot s
+__device__ inline int slot_entry(const Problem &P, int s) { return P.ctr[P.cid[s]].entry; }
+
+// The problem description of a kernel whose only argument is a Problem, read
+// through a pointer into the kernel-argument segment that the compiler cannot
+// follow across loop iterations: its fields are then loaded (scalar loads
+// from the constant cache) where an item uses them, instead of being held in
+// scalar registers across the whole item loop, which overflowed them into
+// vector-register lanes.
+__device__ inline const Problem &kernarg_problem(const Problem &P) {
+#ifdef __HIP_DEVICE_COMPILE__
+  typedef const __attribute__((address_space(4))) Problem CP;
+  CP *pk = (CP *)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(pk));
+  return *(const Problem *)pk;
+#else
+  return P;
+#endif
+}
+
 // Each workgroup takes a contiguous range of work items; its waves take every
 // nw-th item of it, so at any time they work on neighbouring parents, mostly
-// of one container and parameter row.  The LDS holds the table of the
-// parameter row of the range's first item (loaded once; items of another
-// row read their table from global memory), and there is no workgroup
-// barrier in the item loop: each wave runs through its items on its own.
-// The slot of an item is found by a search only when the wave's items leave
-// the current slot's range.
+// of one container and parameter row.  The range is cut into segments of
+// consecutive slots of one parameter row (usually a single one); at the
+// start of a segment the workgroup stages that row's table in LDS (two
+// barriers), and inside a segment there is no workgroup barrier: each wave
+// runs through its items on its own.  The slot of an item is found by a
+// search only when the wave's items leave the current slot's range.
 template <int L, int GRAM>
 __global__ void __launch_bounds__(256) k_children(Problem P) {
   extern __shared__ double lds_raw[];
   __shared__ int pidmap[Dims<L>::MU];
-  __shared__ int s_entry;
   double *tabl = lds_raw;
   // the wave index is uniform in a wave: keep it (and all per-item
   // bookkeeping derived from it) in scalar registers
   const int nw = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw + kTabRowsLds * kTabStride +
+  WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw + (size_t)P.tab_rows * kTabStride +
                                                   (size_t)wv * P.lds_wave_doubles);
   const int total = P.counters[2];
   const int per = (total + gridDim.x - 1) / gridDim.x;
   const int i0 = blockIdx.x * per, i1 = min(i0 + per, total);
   if (i0 >= i1) return;  // uniform in the workgroup
   build_pidmap<L>(pidmap, threadIdx.x, blockDim.x);
-  if (threadIdx.x == 0) {
-    const int e0 = P.ctr[P.cid[item_slot(P, i0)]].entry;
-    s_entry = (P.entries[e0].J <= kTabRowsLds) ? e0 : -1;
-  }
-  __syncthreads();
-  const int ent = s_entry;
-  if (ent >= 0) {
-    const Entry E0 = P.entries[ent];
-    const double *src = P.tab + E0.tab_off;
-    for (int i = threadIdx.x; i < E0.J * kTabStride; i += blockDim.x) tabl[i] = src[i];
-  }
-  __syncthreads();
-  int s = -1, lo = 0, hi = 0;  // current slot and its item range [lo, hi)
+  int s = item_slot(P, i0), lo = P.woff[s], hi = P.woff[s + 1];  // current slot, its items
+  int w = i0 + wv, seg = i0, loaded = -1;
 #pragma unroll 1
-  for (int w = i0 + wv; w < i1; w += nw) {
-    if (w >= hi) {  // find the slot holding item w (woff is non-decreasing)
-      int a = s < 0 ? 0 : s + 1, b = P.W;  // woff[a] <= w < woff[b]
-      while (b - a > 1) {
-        const int mid = (a + b) >> 1;
-        if (P.woff[mid] <= w) a = mid; else b = mid;
+  while (seg < i1) {
+    // segment [seg, seg_hi): slots from s on while they hold items of row e
+    // (slots without items are passed over)
+    const int e = slot_entry(P, s);
+    int t = s + 1;
+    while (t < P.W && P.woff[t] < i1 && (P.woff[t + 1] == P.woff[t] || slot_entry(P, t) == e)) ++t;
+    const int seg_hi = (t < P.W && P.woff[t] < i1) ? P.woff[t] : i1;
+    if (e != loaded) {
+      __syncthreads();  // every wave is done with the previous table
+      const Entry E0 = P.entries[e];
+      const double *src = P.tab + E0.tab_off;
+      for (int i = threadIdx.x; i < E0.J * kTabStride; i += blockDim.x) tabl[i] = src[i];
+      __syncthreads();
+      loaded = e;
+    }
+#pragma unroll 1
+    for (; w < seg_hi; w += nw) {
+      if (w >= hi) {  // find the slot holding item w (woff is non-decreasing)
+        int a = s + 1, b = P.W;  // woff[a] <= w < woff[b]
+        while (b - a > 1) {
+          const int mid = (a + b) >> 1;
+          if (P.woff[mid] <= w) a = mid; else b = mid;
+        }
+        s = a;
+        lo = P.woff[s];
+        hi = P.woff[s + 1];
       }
-      s = a;
+      do_item<L, GRAM>(S, kernarg_problem(P), pidmap, s, w - lo, tabl);
+    }
+    // the next segment starts at slot t (its first item is seg_hi)
+    seg = seg_hi;
+    if (seg < i1) {
+      s = t;
       lo = P.woff[s];
       hi = P.woff[s + 1];
     }
-    const int e = P.ctr[P.cid[s]].entry;
-    if (e == ent)
-      do_item<L, GRAM>(S, P, pidmap, s, w - lo, tabl);
-    else
-      do_item<L, GRAM>(S, P, pidmap, s, w - lo, P.tab + P.entries[e].tab_off);
   }
 }
 
@@ -818,14 +858,29 @@ hipError_t launch_root_t(const Problem &p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Dynamic LDS of the evaluation kernel: the largest table plus one WaveLds
+// per wave, as many waves (up to 4) as fit in 64 KiB, or one wave in the
+// device's limit when the table is larger.  Returns 0 if not even that fits.
+template <int L>
+size_t eval_lds_t(const Problem &p, int *waves_out, int *wave_doubles_out) {
+  const size_t wave_b = sizeof(double) * wave_lds_doubles<L>(p.ff_identity);
+  const size_t tab_b = sizeof(double) * (size_t)p.tab_rows * kTabStride, fixed = 2048;
+  size_t budget = 65536;
+  if (tab_b + wave_b + fixed > budget) budget = p.lds_limit > 0 ? (size_t)p.lds_limit : 65536;
+  if (tab_b + wave_b + fixed > budget) return 0;
+  int waves = (int)((budget - fixed - tab_b) / wave_b);
+  waves = waves > 4 ? 4 : waves;
+  if (waves_out) *waves_out = waves;
+  if (wave_doubles_out) *wave_doubles_out = (int)(wave_b / sizeof(double));
+  return tab_b + (size_t)waves * wave_b;
+}
+
 template <int L, int GRAM>
 hipError_t launch_eval_t(Problem p, int grid, hipStream_t s) {
-  p.lds_wave_doubles = (int)wave_lds_doubles<L>(p.ff_identity);
-  // as many waves per workgroup (up to 4) as fit in 64 KiB with the table
-  const size_t avail = 65536 - 2048 - sizeof(double) * kTabRowsLds * kTabStride;
-  int waves = (int)(avail / (sizeof(double) * p.lds_wave_doubles));
-  waves = waves < 1 ? 1 : (waves > 4 ? 4 : waves);
-  size_t sh = sizeof(double) * ((size_t)kTabRowsLds * kTabStride + (size_t)waves * p.lds_wave_doubles);
+  int waves = 0, wd = 0;
+  const size_t sh = eval_lds_t<L>(p, &waves, &wd);
+  if (sh == 0) return hipErrorInvalidValue;
+  p.lds_wave_doubles = wd;
   hipLaunchKernelGGL((k_children<L, GRAM>), dim3(grid), dim3(64 * waves), sh, s, p);
   return hipGetLastError();
 }
@@ -863,6 +918,14 @@ hipError_t launch_root(const Problem &p, hipStream_t s) {
     case 0: return launch_root_l<0>(p, s);
     case 1: return launch_root_l<1>(p, s);
     default: return launch_root_l<2>(p, s);
+  }
+}
+
+size_t eval_lds_bytes(const Problem &p) {
+  switch (p.L) {
+    case 0: return eval_lds_t<0>(p, nullptr, nullptr);
+    case 1: return eval_lds_t<1>(p, nullptr, nullptr);
+    default: return eval_lds_t<2>(p, nullptr, nullptr);
   }
 }
 

@@ -119,6 +119,43 @@ def test_children_match_oracle_rectangles(ctx, P, ff_name, ch):
             assert abs(keys[i, k] - ek) <= 1e-12 * np.abs(ref).sum() + 1e-7 * ek, (i, k)
 
 
+def _children_against_oracle(c, P, row, l, ff, L, codes, tol=1e-12):
+    q2n, keys = c.children(row, l, P.PH, ff, L, codes)
+    oc = O.Container(ff, L, t=row[0], tp=row[1], mu=row[2], T=row[3], Omega=row[4], lx=l[0],
+                     ly=l[1], channel=O.PH)
+    for i, (d, ix, iy) in enumerate(codes):
+        w = 2 * math.pi / 2 ** d
+        for k in range(4):
+            x0 = -math.pi + ix * w + (k & 1) * w / 2
+            y0 = -math.pi + iy * w + (k >> 1) * w / 2
+            qn, ref = oc.region(x0, x0 + w / 2, y0, y0 + w / 2)
+            assert np.abs(q2n[i, k] - ref).max() <= tol * np.abs(ref).max(), (row, i, k)
+
+
+def test_children_with_a_long_frequency_table(ctx, P):
+    """T = 1e-4 against a band of 6.3: a table of 129 rows, staged whole in LDS"""
+    codes = np.array([(0, 0, 0), (5, 7, 20), (9, 300, 100)])
+    _children_against_oracle(ctx, P, (1.0, -0.3, -1.1, 1e-4, 0.05), (2.88, 0.26), W.ff_box(1), 1,
+                             codes)
+
+
+def test_children_with_a_table_past_64k_of_lds(P):
+    """T = 1.5e-6: 177 table rows (25.5 KB) beside the per-wave scratch of a
+    general 25-function set (38.6 KB) exceed 64 KiB; the workgroup then takes
+    one wave and the device's LDS limit, or the call is refused with a clear
+    error where the device has no more than 64 KiB per workgroup"""
+    rng = np.random.default_rng(11)
+    ff = np.linalg.qr(rng.normal(size=(25, 25)))[0][:6]  # 6 orthonormal rows, not the box
+    codes = np.array([(6, 40, 17)])
+    with P.Context() as c:
+        try:
+            _children_against_oracle(c, P, (1.0, -0.3, -1.1, 1.5e-6, 0.05), (2.88, 0.26), ff, 2,
+                                     codes)
+        except P.PaidError as e:
+            assert "does not fit in LDS" in str(e), e
+            print("refused:", e)
+
+
 # ------------------------------------------------------------------ full integrations
 def test_c1_full_workload(ctx, P):
     """8x8 q, FF5, pp+ph at the workload's rtol 1e-4 and at 1e-6."""
