@@ -47,7 +47,7 @@ K_FLOPS_PER_NODE = 80
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
 TRAFFIC_BYTES_PER_ITEM = 2404
-TRAFFIC_SOURCES_SHA256 = "d71fcb245e121a137121265179c8497dc623d3d125b01bd0414ca118b26a1c2c"
+TRAFFIC_SOURCES_SHA256 = "b41ffa9386a8be8067b54a11d2508d69a9e1d0a628eccd4b35a57675e49f0c18"
 
 
 def kernel_sources_sha256() -> str:
