@@ -21,6 +21,9 @@ namespace {
 
 constexpr int kBins = 512;
 constexpr int kSelThreads = 256;
+// region codes hold ix and iy in 28 bits each: a rectangle of depth 28 (side
+// 2 pi / 2^28) is the smallest one a code can hold and is never split
+constexpr int kMaxDepth = 28;
 
 __device__ inline double block_sum(double v, double *sh) {
   // fixed-order reduction: deterministic for a fixed block size
@@ -370,7 +373,23 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     seenpart += totp;
     if (out >= s_k) break;
   }
-  if (t == 0) P.selcnt[s] = out < s_k ? out : s_k;
+  // a selected leaf at the deepest level a code can hold cannot be split:
+  // the container stops with the budget flag, as on an exhausted pool
+  const int ksel = out < s_k ? out : s_k;
+  __syncthreads();  // sel is complete
+  int deep = 0;
+  for (int j = t; j < ksel; j += blockDim.x)
+    deep |= code_depth(P.code[base + sel[j]]) >= kMaxDepth ? 1 : 0;
+  deep = __syncthreads_or(deep);
+  if (t == 0) {
+    if (deep) {
+      P.selcnt[s] = 0;
+      P.flags[s] |= 2;
+      P.state[s] = SLOT_DONE;
+    } else {
+      P.selcnt[s] = ksel;
+    }
+  }
 }
 
 __global__ void k_worklist(Problem P) {

@@ -250,6 +250,22 @@ def test_budget_exhaustion_reports_noconv(P):
     assert np.isfinite(out).all() and (e > 0).any()
 
 
+def test_refinement_stops_at_the_deepest_code(P):
+    """A Gaussian of width 1e-10 centred on a corner that every level keeps
+    as a node: the error estimate never drops below the tolerance before the
+    rectangles reach the smallest side a region code holds (2 pi / 2^28);
+    the container then stops with the budget flag (ENOCONV) instead of
+    splitting further (at most four splits per round, so that the region
+    budget is not what stops it)."""
+    with P.Context(kind=P.GAUSS, gauss=(0.0, 0.0, 1e-10), max_regions=1 << 14, batch=1,
+                   batch_max=4) as c:
+        out, e, st, rc = c.integrate([[1, 0, 0, 0.1, 0.1]], [[0.0, 0.0]], W.ff_box(0), 0,
+                                     channels=P.PH, rtol=1e-8, err=True)
+    assert rc == P.ENOCONV and st["not_converged"] == 1
+    assert st["max_depth"] == 28 and st["regions"] < (1 << 14)
+    assert np.isfinite(out).all() and np.isfinite(e).all()
+
+
 def test_results_are_bitwise_reproducible(ctx, P):
     cfg = W.config("C1")
     a, _, _, _ = ctx.integrate(cfg["params"], cfg["q"][:20], cfg["ff"], 1, rtol=1e-6)
