@@ -160,7 +160,10 @@ int paid_create(struct paid_ctx **out, const paid_config *cfg);
  *   err_out  NULL or the same shape: per pair, sum over leaves of
  *            |Q_N - Q_2N|
  *   stats    NULL or filled on return
- * Returns PAID_OK, PAID_ENOCONV, or an error (outputs then undefined). */
+ * n_params >= 1 and n_q >= 1 (an empty batch is PAID_EINVAL).
+ * Returns PAID_OK, PAID_ENOCONV (some container hit max_regions or the
+ * smallest rectangle a region code holds, side 2 pi / 2^28; its output is
+ * its sum over the leaves it has), or an error (outputs then undefined). */
 int paid_integrate(struct paid_ctx *ctx, const paid_params *params, int n_params,
                    const double *q, int n_q, const double *ff, int n_ff, int ff_L,
                    unsigned channels, double rtol, double atol, double *out,
@@ -168,7 +171,9 @@ int paid_integrate(struct paid_ctx *ctx, const paid_params *params, int n_params
 
 /* Frequency-summed kernel g = K_j(a, b) of one parameter row at n energy
  * pairs (the closed-form frequency sum of Sec. 2 as the library evaluates
- * it).  channel: PAID_PP or PAID_PH.  a, b, out: [n]. */
+ * it).  channel: PAID_PP or PAID_PH.  a, b, out: [n], n >= 0 (NULL allowed
+ * when n = 0); energies beyond the band bound 4|t| + 4|t'| + |mu| are
+ * PAID_EINVAL. */
 int paid_kernel_eval(struct paid_ctx *ctx, const paid_params *p, unsigned channel,
                      const double *a, const double *b, int n, double *out);
 

@@ -740,7 +740,7 @@ int paid_kernel_eval(paid_ctx *c, const paid_params *p, unsigned channel, const 
                      const double *b, int n, double *out) {
   if (!c) return PAID_EINVAL;
   c->err.clear();
-  if (!p || !a || !b || !out || n < 0) return fail(c, PAID_EINVAL, "bad arguments");
+  if (!p || n < 0 || (n > 0 && (!a || !b || !out))) return fail(c, PAID_EINVAL, "bad arguments");
   if (channel != PAID_PP && channel != PAID_PH) return fail(c, PAID_EINVAL, "channel must be PAID_PP or PAID_PH");
   if (c->cfg.kind > 1) return fail(c, PAID_EINVAL, "kernel_eval needs a bubble kind");
   HIPCHK(c, hipSetDevice(c->cfg.device));

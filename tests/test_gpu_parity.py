@@ -285,6 +285,23 @@ def test_invalid_arguments_are_rejected(ctx, P):
         assert ei.value.code == P.EINVAL
 
 
+def test_empty_inputs(ctx, P):
+    """an empty batch is refused (EINVAL); an empty list of energies or of
+    transfer momenta to contract gives empty results"""
+    p = [[1.0, -0.25, -0.95, 0.05, 0.1]]
+    for params, q in ((p, np.zeros((0, 2))), (np.zeros((0, 5)), [[0.1, 0.2]])):
+        with pytest.raises(P.PaidError) as ei:
+            ctx.integrate(params, q, W.ff_box(1), 1)
+        assert ei.value.code == P.EINVAL
+    with pytest.raises(P.PaidError) as ei:
+        ctx.children(p[0], (0.1, 0.2), P.PH, W.ff_box(1), 1, np.zeros((0, 3), dtype=np.int32))
+    assert ei.value.code == P.EINVAL
+    assert ctx.kernel(p[0], [], []).shape == (0,)
+    z = np.zeros((0, 9, 9))
+    dP, dC, dD = ctx.contract(np.zeros((0, 2, 9, 9)), z, z, z)
+    assert dP.shape == dC.shape == dD.shape == (0, 9, 9)
+
+
 def test_full_size_workload_sampled(P):
     """The benchmark's workload at full size (23,040 containers, one call) in
     the benchmark's launch configuration (graph-replayed rounds, the shipped
