@@ -111,7 +111,10 @@ typedef struct {
                            the evaluation launch) as HIP graphs and replay
                            them every round */
   int eval_wg_per_cu;   /* workgroups of the region-evaluation launch per
-                           compute unit (0: 32) */
+                           compute unit (0: 16 per workgroup the kernel's
+                           occupancy fits on a compute unit); the work items
+                           of a round are split over them in geometrically
+                           shrinking ranges */
 } paid_config;
 
 /* one parameter row: dispersion, temperature and flow scale */

@@ -36,7 +36,7 @@ def sample(cfg, fraction, seed=7):
 
 
 def tune(workload="C2", fraction=0.25, batches=(8, 32), batch_maxes=(1024, 4096, 16384),
-         actives=(0,), grids=(16, 32, 64), repeat=2, log=print):
+         actives=(0,), grids=(0, 32, 64), repeat=2, log=print):
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
     import paid_1610_09991_amd as P

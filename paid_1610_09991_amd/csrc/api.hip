@@ -636,7 +636,12 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, cfg.device) == hipSuccess && v > 0)
       dev_cus = v;
   }
-  const int eval_grid = dev_cus * (cfg.eval_wg_per_cu > 0 ? cfg.eval_wg_per_cu : 32);
+  // guided partition over the workgroups resident at once; the default grid
+  // (16 per resident slot) covers 4 e^16 work items per launch before its
+  // last workgroup has to take a remainder of more than four
+  const int occ = eval_occupancy(P);
+  P.eval_slots = occ * dev_cus;
+  const int eval_grid = dev_cus * (cfg.eval_wg_per_cu > 0 ? cfg.eval_wg_per_cu : 16 * occ);
   long rounds = 0, eval_items = 0;
   double eval_ms = 0.0;
   // one device round in three parts: admission, roots, selection and work

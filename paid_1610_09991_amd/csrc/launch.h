@@ -57,6 +57,7 @@ struct Problem {      // everything the round kernels need, passed by value
   int lds_wave_doubles;       // per-wave LDS of the evaluation kernel (set at launch)
   int tab_rows;               // rows of the largest frequency-sum table (the LDS table)
   int lds_limit;              // bytes of LDS a workgroup may use on the device
+  int eval_slots;             // evaluation workgroups resident at once (0: even partition)
   uint64_t *code;             // [W*cap]
   double *key;                // [W*cap]
   double *Q;                  // [W*cap*MU]
@@ -138,6 +139,8 @@ hipError_t launch_select(const Problem &p, hipStream_t s);
 hipError_t launch_worklist(const Problem &p, hipStream_t s);
 // dynamic LDS bytes of the evaluation kernel for p (0: the table does not fit)
 size_t eval_lds_bytes(const Problem &p);
+// evaluation workgroups that fit on one compute unit at once for p
+int eval_occupancy(const Problem &p);
 hipError_t launch_eval(const Problem &p, int grid, hipStream_t s);
 hipError_t launch_update(const Problem &p, hipStream_t s);
 hipError_t launch_finalize(const Problem &p, hipStream_t s);

@@ -112,8 +112,9 @@ __device__ inline int tab_index(const Entry &e, double ax) {
 // the polynomial of x's interval: Horner at tx carries the quotient
 // coefficients, Horner of those at ty is the divided difference (no
 // subtraction of values; there |ty| <= 1.5, a tenth of the radius of
-// convergence in units of the half-width).  Both forms run in one loop
-// with the second row and argument chosen per lane, so lanes never diverge.
+// convergence in units of the half-width).  Both forms are written as one
+// loop with the second row and argument chosen per lane (the compiler moves
+// the chain that a lane's form does not use into a branch).
 __device__ inline double K_eval(const Entry &e, const double *tab, int ch, double a, double b) {
   const double y0 = ch ? b : -b;
   const double f = a < 0.0 ? -1.0 : 1.0;

@@ -796,8 +796,25 @@ __global__ void __launch_bounds__(256) k_children(Problem P) {
   WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw + (size_t)P.tab_rows * kTabStride +
                                                   (size_t)wv * P.lds_wave_doubles);
   const int total = P.counters[2];
-  const int per = (total + gridDim.x - 1) / gridDim.x;
-  const int i0 = blockIdx.x * per, i1 = min(i0 + per, total);
+  int i0, i1;
+  if (P.eval_slots > 0) {
+    // guided partition: workgroup b starts at item total (1 - k^b) with
+    // k = 1 - 1/S, S the workgroups resident at once, so the ranges shrink
+    // geometrically and the workgroups dispatched last (the tail of the
+    // launch) are short; k is lowered where the grid would otherwise leave
+    // its last workgroup more than four items
+    const double keep = fmin(1.0 - 1.0 / (double)P.eval_slots,
+                             exp(log(4.0 / fmax((double)total, 4.0)) / (double)gridDim.x));
+    auto start = [&](int b) -> int {
+      return b >= (int)gridDim.x ? total : (int)((double)total * (1.0 - pow(keep, (double)b)));
+    };
+    i0 = start(blockIdx.x);
+    i1 = min(start(blockIdx.x + 1), total);
+  } else {
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    i0 = blockIdx.x * per;
+    i1 = min(i0 + per, total);
+  }
   if (i0 >= i1) return;  // uniform in the workgroup
   build_pidmap<L>(pidmap, threadIdx.x, blockDim.x);
   int s = item_slot(P, i0), lo = P.woff[s], hi = P.woff[s + 1];  // current slot, its items
@@ -876,6 +893,18 @@ size_t eval_lds_t(const Problem &p, int *waves_out, int *wave_doubles_out) {
 }
 
 template <int L, int GRAM>
+int eval_occupancy_t(Problem p) {
+  int waves = 0, wd = 0;
+  const size_t sh = eval_lds_t<L>(p, &waves, &wd);
+  if (sh == 0) return 1;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_children<L, GRAM>),
+                                                   64 * waves, sh) != hipSuccess || n < 1)
+    n = 1;
+  return n;
+}
+
+template <int L, int GRAM>
 hipError_t launch_eval_t(Problem p, int grid, hipStream_t s) {
   int waves = 0, wd = 0;
   const size_t sh = eval_lds_t<L>(p, &waves, &wd);
@@ -903,6 +932,16 @@ hipError_t launch_root_l(const Problem &p, hipStream_t s) {
 }
 
 template <int L>
+int eval_occupancy_l(const Problem &p) {
+  switch (gram_mode(p)) {
+    case kSep: return eval_occupancy_t<L, kSep>(p);
+    case PAID_FP32: return eval_occupancy_t<L, PAID_FP32>(p);
+    case PAID_BF16X3: return eval_occupancy_t<L, PAID_BF16X3>(p);
+    default: return eval_occupancy_t<L, PAID_FP64>(p);
+  }
+}
+
+template <int L>
 hipError_t launch_eval_l(const Problem &p, int grid, hipStream_t s) {
   switch (gram_mode(p)) {
     case kSep: return launch_eval_t<L, kSep>(p, grid, s);
@@ -926,6 +965,14 @@ size_t eval_lds_bytes(const Problem &p) {
     case 0: return eval_lds_t<0>(p, nullptr, nullptr);
     case 1: return eval_lds_t<1>(p, nullptr, nullptr);
     default: return eval_lds_t<2>(p, nullptr, nullptr);
+  }
+}
+
+int eval_occupancy(const Problem &p) {
+  switch (p.L) {
+    case 0: return eval_occupancy_l<0>(p);
+    case 1: return eval_occupancy_l<1>(p);
+    default: return eval_occupancy_l<2>(p);
   }
 }
 
