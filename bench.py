@@ -46,8 +46,8 @@ K_FLOPS_PER_NODE = 80
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2404
-TRAFFIC_SOURCES_SHA256 = "b41ffa9386a8be8067b54a11d2508d69a9e1d0a628eccd4b35a57675e49f0c18"
+TRAFFIC_BYTES_PER_ITEM = 2405
+TRAFFIC_SOURCES_SHA256 = "dfbcc3bf122d9b3e7750173c13296546bf0399aa5488095a49c3e6c6ec506bb6"
 
 
 def kernel_sources_sha256() -> str:
