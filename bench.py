@@ -115,6 +115,10 @@ def main():
     ap.add_argument("--seed-model", default=None,
                     help="model file of the learned seeding (default: the shipped one)")
     ap.add_argument("--no-seed", action="store_true", help="time the plain batched scheme only")
+    ap.add_argument("--no-half-zone", action="store_true",
+                    help="skip the extra variant that integrates the half zone p_y >= 0 (an "
+                         "exact symmetry of the integrand, not the paper's scheme; never the "
+                         "headline value)")
     ap.add_argument("--tuned", default=None,
                     help="autotuner profile (JSON) whose config to apply; default: the shipped "
                          "profile of the workload if there is one")
@@ -163,7 +167,7 @@ def main():
     ctx = P.Context(stream=stream.cuda_stream, profile=1, precision=prec, graph=args.graph,
                     gram=P.GRAM_SEPARABLE if args.gram == "separable" else P.GRAM_MFMA, **tuned)
     out = torch.empty((len(params), len(q), nch, M, M), dtype=torch.float64, device=dev)
-    run = lambda o: ctx.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=o)
+    run = lambda o, c=ctx: c.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=o)
 
     # learned seeding: the shipped model (trained on the library's own trees,
     # see paid_1610_09991_amd/seed_model.py) with its tuned threshold
@@ -176,20 +180,20 @@ def main():
                  "trees": meta["trees"], "train_seconds": meta["train_seconds"],
                  "mse_held_out": meta["mse_held_out"]}
 
-    def timed(seeded, tag):
+    def timed(seeded, tag, c=ctx, run=run):
         if seeded:
-            ctx.set_seed_model(w_seed, kappa=model["kappa"])
+            c.set_seed_model(w_seed, kappa=model["kappa"])
         else:
-            ctx.set_seed_model(None)
+            c.set_seed_model(None)
         for i in range(args.warmup):
-            _, _, st, rc = run(out)
+            _, _, st, rc = run(out, c)
             print(f"# {tag} warmup {i}: {st['seconds']:.3f} s, regions {st['regions']}, "
                   f"evals {st['kernel_evals']:.4g}, rc {rc}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sts = []
         for i in range(args.steps):
-            _, _, st, rc = run(out)
+            _, _, st, rc = run(out, c)
             sts.append(st)
             print(f"# {tag} step {i}: {st['seconds']:.3f} s, regions {st['regions']}, "
                   f"evals {st['kernel_evals']:.4g}, rc {rc}", file=sys.stderr, flush=True)
@@ -211,6 +215,20 @@ def main():
                                        "regions": st_seed[-1]["regions"],
                                        "seed_seconds": st_seed[-1]["seed_seconds"]}
         head, dt, stats = "batched_learned", dt_seed, st_seed
+    if not args.no_half_zone:
+        # the same integrals from the half zone p_y >= 0 (the integrand is even
+        # under p -> -p): an extra data point beside the paper's full-zone scheme
+        hctx = P.Context(stream=stream.cuda_stream, profile=1, precision=prec, graph=args.graph,
+                         gram=P.GRAM_SEPARABLE if args.gram == "separable" else P.GRAM_MFMA,
+                         symmetry=1, **tuned)
+        hout = torch.empty_like(out)
+        run_h = lambda o, c: c.integrate(params, q, ff, L, P.PP | P.PH, rtol=cfg["rtol"], out=hout)
+        dt_half, st_half = timed(False, "batched+half-zone", hctx, run_h)
+        hctx.close()
+        variants["batched_half_zone"] = {"value": n_int * args.steps / dt_half,
+                                         "ms_per_step": 1e3 * dt_half / args.steps,
+                                         "kernel_evals": st_half[-1]["kernel_evals"],
+                                         "regions": st_half[-1]["regions"]}
     ms = 1e3 * dt / args.steps
     value = n_int * args.steps / dt
 

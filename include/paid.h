@@ -115,6 +115,15 @@ typedef struct {
                            occupancy fits on a compute unit); the work items
                            of a round are split over them in geometrically
                            shrinking ranges */
+  int symmetry;         /* 1: integrate over the half zone p_y >= 0 only.  The
+                           integrand of both bubbles is even under p -> -p
+                           (it swaps the energies eps(l/2 + p) and
+                           eps(l/2 - p), and K_j is symmetric in them), so a
+                           pair of box functions of odd joint parity (an odd
+                           number of sine factors) integrates to exactly 0
+                           and any other pair to twice its half-zone
+                           integral.  Not part of the paper's scheme; not
+                           with PAID_GAUSS, learned seeding or tree labels */
 } paid_config;
 
 /* one parameter row: dispersion, temperature and flow scale */

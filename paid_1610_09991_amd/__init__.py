@@ -38,7 +38,7 @@ class Config(C.Structure):
                 ("kind", C.c_int), ("nu", C.c_double), ("max_regions", C.c_long),
                 ("max_active", C.c_int), ("pool_gib", C.c_double),
                 ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int),
-                ("graph", C.c_int), ("eval_wg_per_cu", C.c_int)]
+                ("graph", C.c_int), ("eval_wg_per_cu", C.c_int), ("symmetry", C.c_int)]
 
 
 class Params(C.Structure):

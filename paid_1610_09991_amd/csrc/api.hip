@@ -363,6 +363,9 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
   if (!(cfg.nu >= 0)) return fail(nullptr, PAID_EINVAL, "nu must be >= 0");
   if (cfg.eval_wg_per_cu < 0 || cfg.eval_wg_per_cu > 1024)
     return fail(nullptr, PAID_EINVAL, "eval_wg_per_cu must be 0..1024");
+  if (cfg.symmetry != 0 && cfg.symmetry != 1) return fail(nullptr, PAID_EINVAL, "symmetry must be 0 or 1");
+  if (cfg.symmetry && cfg.kind == PAID_GAUSS)
+    return fail(nullptr, PAID_EINVAL, "the Gaussian test integrand is not even under p -> -p");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev == 0) return fail(nullptr, PAID_EDEVICE, "no HIP device");
@@ -587,6 +590,9 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
 
   // learned seeding: model features of every container, then the model
   const bool want_labels = c->lab_out != nullptr || c->feat_out != nullptr;
+  if (cfg.symmetry && (c->seed_on || want_labels))
+    return fail(c, PAID_EINVAL, "the half-zone mode takes neither a seed model nor tree labels");
+  P.sym = cfg.symmetry;
   double seed_s = 0.0;
   if (c->seed_on || want_labels) {
     auto ts = std::chrono::steady_clock::now();

@@ -58,6 +58,7 @@ struct Problem {      // everything the round kernels need, passed by value
   int tab_rows;               // rows of the largest frequency-sum table (the LDS table)
   int lds_limit;              // bytes of LDS a workgroup may use on the device
   int eval_slots;             // evaluation workgroups resident at once (0: even partition)
+  int sym;                    // 1: half zone p_y >= 0 with the parity factors of the pairs
   uint64_t *code;             // [W*cap]
   double *key;                // [W*cap]
   double *Q;                  // [W*cap*MU]

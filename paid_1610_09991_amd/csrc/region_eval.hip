@@ -99,6 +99,21 @@ __device__ inline int prod_index(int a, int c) {  // (a, c) -> index of u_a u_c
   return a * NB - a * (a - 1) / 2 + (c - a);
 }
 
+// parity of box function m = a NB + b under p -> -p: 1 if it has one sine
+// factor (u_{2k} = sqrt2 sin kx is odd, 1 and the cosines are even)
+template <int NB>
+__device__ inline int box_odd(int m) {
+  const int a = m / NB, b = m - a * NB;
+  return ((a > 0 && !(a & 1)) ? 1 : 0) ^ ((b > 0 && !(b & 1)) ? 1 : 0);
+}
+
+// weight of a box pair in the half-zone mode: 0 for odd joint parity (the
+// full-zone integral vanishes), else 2 (the two halves are equal)
+template <int NB>
+__device__ inline double half_zone_factor(int m, int n) {
+  return (box_odd<NB>(m) ^ box_odd<NB>(n)) ? 0.0 : 2.0;
+}
+
 // sin and cos of |x| <= pi (+ rounding): reduction by pi/2 in two parts
 // (Cody-Waite; q*pi/2 is exact for |q| <= 2) to |r| <= pi/4, then the Taylor
 // series of sin and cos to degree 17/18 (truncation below 1e-19 there).
@@ -219,8 +234,8 @@ __device__ void sep_stage1(WaveLds<L> &S, int nco, int nrow) {
 // Stage 2 for child (cx, cy), then the form-factor pairs (identity basis) or
 // the full box Gram (general sets) scaled by the area factor fa.
 template <int L>
-__device__ void sep_stage2(WaveLds<L> &S, const Problem &P, const int *pidmap, int cx, int cy,
-                           double fa) {
+__device__ void sep_stage2(WaveLds<L> &S, const Problem &P, const int *pidmap, const int *podd,
+                           int cx, int cy, double fa) {
   constexpr int NB = Dims<L>::NB, NP = Dims<L>::NP, MB = Dims<L>::MB, MU = Dims<L>::MU;
   const int lane = lane_id();
   for (int idx = lane; idx < NP * NP; idx += 64) {
@@ -240,17 +255,19 @@ __device__ void sep_stage2(WaveLds<L> &S, const Problem &P, const int *pidmap, i
   if (P.ff_identity) {
     for (int pid = lane; pid < MU; pid += 64) {
       int jk = pidmap[pid];
-      double q2 = S.g2[jk];
-      S.cq[pid] = fa * q2;
-      S.ce[pid] = fa * (q2 - S.g1[jk]);
+      double q2 = S.g2[jk], f = fa;
+      if (P.sym) f = podd[pid] ? 0.0 : 2.0 * fa;
+      S.cq[pid] = f * q2;
+      S.ce[pid] = f * (q2 - S.g1[jk]);
     }
   } else {
     for (int idx = lane; idx < MB * MB; idx += 64) {
       int m = idx / MB, n = idx - m * MB;
       int jk = prod_index<NB>(m / NB, n / NB) * NP + prod_index<NB>(m % NB, n % NB);
-      double q2 = S.g2[jk];
-      S.tq[idx] = fa * q2;
-      S.ts[idx] = fa * (q2 - S.g1[jk]);
+      double q2 = S.g2[jk], f = fa;
+      if (P.sym) f = half_zone_factor<NB>(m, n) * fa;
+      S.tq[idx] = f * q2;
+      S.ts[idx] = f * (q2 - S.g1[jk]);
     }
   }
   wave_sync();
@@ -298,6 +315,11 @@ template <int L>
 __device__ inline void gram_put(WaveLds<L> &S, const Problem &P, int i, int j, double q, double e) {
   constexpr int MB = Dims<L>::MB;
   if (i < MB && j < MB && i <= j) {
+    if (P.sym) {
+      const double f = half_zone_factor<Dims<L>::NB>(i, j);
+      q *= f;
+      e *= f;
+    }
     if (P.ff_identity) {
       int pid = pair_index(i, j, MB);
       S.cq[pid] = q;
@@ -500,10 +522,10 @@ __device__ double store_region(WaveLds<L> &S, const Problem &P, int s, long ri, 
 constexpr int kSep = 3;
 
 template <int L, int GRAM>
-__device__ void eval_rect(WaveLds<L> &S, const Problem &P, const int *pidmap, int nco, int cx,
-                          int cy, double fa) {
+__device__ void eval_rect(WaveLds<L> &S, const Problem &P, const int *pidmap, const int *podd,
+                          int nco, int cx, int cy, double fa) {
   if (GRAM == kSep) {
-    sep_stage2<L>(S, P, pidmap, cx, cy, fa);
+    sep_stage2<L>(S, P, pidmap, podd, cx, cy, fa);
   } else {
     gram_mfma<L, GRAM>(S, P, nco, 8 * cx, 8 * cy, fa);
   }
@@ -511,14 +533,16 @@ __device__ void eval_rect(WaveLds<L> &S, const Problem &P, const int *pidmap, in
 }
 
 // pair index -> index into the x-sum matrix of the separable form
+// and whether the pair has odd joint parity (half-zone mode)
 template <int L>
-__device__ void build_pidmap(int *map, int tid, int nthr) {
+__device__ void build_pidmap(int *map, int *odd, int tid, int nthr) {
   constexpr int NB = Dims<L>::NB, MB = Dims<L>::MB, NP = Dims<L>::NP, MU = Dims<L>::MU;
   for (int pid = tid; pid < MU; pid += nthr) {
     int m = 0, k = pid;
     while (k >= MB - m) { k -= MB - m; ++m; }
     int n = m + k;
     map[pid] = prod_index<NB>(m / NB, n / NB) * NP + prod_index<NB>(m % NB, n % NB);
+    odd[pid] = box_odd<NB>(m) ^ box_odd<NB>(n);
   }
 }
 
@@ -604,12 +628,12 @@ __device__ int seed_admit(const Problem &P, int s, int c, double *spyr) {
 template <int L, int GRAM>
 __global__ void __launch_bounds__(64) k_root(Problem P) {
   extern __shared__ double lds_raw[];
-  __shared__ int pidmap[Dims<L>::MU];
+  __shared__ int pidmap[Dims<L>::MU], podd[Dims<L>::MU];
   __shared__ double spyr[kPyr];
   WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw);
   const int s = blockIdx.x;
   if (s >= P.W || P.state[s] != SLOT_NEW) return;
-  build_pidmap<L>(pidmap, threadIdx.x, 64);
+  build_pidmap<L>(pidmap, podd, threadIdx.x, 64);
   const int c = P.cid[s];
   // key weights: the pair weights in the weighted mode, else one (the
   // per-integral mode refreshes them with 1/tau every round)
@@ -633,6 +657,7 @@ __global__ void __launch_bounds__(64) k_root(Problem P) {
     placeholder = D > 0 && spyr[0] >= P.seed_thresh;
   }
   double key = 0.0;
+  const int nroot = P.sym ? 2 : 1;  // leaves the container starts from
   if (placeholder) {
     store_zero<L>(P, s, 0, make_code(0, 0, 0));
     for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
@@ -643,22 +668,29 @@ __global__ void __launch_bounds__(64) k_root(Problem P) {
     const Ctr C = P.ctr[c];
     const Entry E = P.entries[C.entry];
     const double *tab = P.tab + E.tab_off;
-    fill_nodes<L>(S, P, C, E, tab, kNF, -kPi, -kPi, kTwoPi);
-    if (GRAM == kSep) sep_stage1<L>(S, kNF, 1);
-    eval_rect<L, GRAM>(S, P, pidmap, kNF, 0, 0, kPi * kPi / (4.0 * kPi * kPi));
-    key = store_region<L>(S, P, s, 0, make_code(0, 0, 0));
-    for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
-      P.val[(long)s * P.MU + pid] = S.cq[pid];
-      if (P.errp) P.errp[(long)s * P.MU + pid] = (double)(float)fabs(S.ce[pid]);
+    // the zone, or in the half-zone mode its two quadrants with p_y >= 0
+    const double wr = P.sym ? kPi : kTwoPi;
+    for (int h = 0; h < nroot; ++h) {
+      fill_nodes<L>(S, P, C, E, tab, kNF, -kPi + h * wr, P.sym ? 0.0 : -kPi, wr);
+      if (GRAM == kSep) sep_stage1<L>(S, kNF, 1);
+      eval_rect<L, GRAM>(S, P, pidmap, podd, kNF, 0, 0, (0.5 * wr) * (0.5 * wr) / (4.0 * kPi * kPi));
+      key += store_region<L>(S, P, s, h, P.sym ? make_code(1, h, 1) : make_code(0, 0, 0));
+      for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
+        const long o = (long)s * P.MU + pid;
+        const double e = (double)(float)fabs(S.ce[pid]);
+        P.val[o] = h ? P.val[o] + S.cq[pid] : S.cq[pid];
+        if (P.errp) P.errp[o] = h ? P.errp[o] + e : e;
+      }
+      wave_sync();
     }
   }
   if (threadIdx.x == 0) {
     P.err[s] = key;
-    P.nleaf[s] = 1;
+    P.nleaf[s] = placeholder ? 1 : nroot;
     P.st_rounds[s] = 0;
     P.st_splits[s] = 0;
-    P.st_evals[s] = placeholder ? 0 : kNF * kNF;
-    P.st_depth[s] = 0;
+    P.st_evals[s] = placeholder ? 0 : nroot * kNF * kNF;
+    P.st_depth[s] = nroot - 1;
     P.flags[s] = P.seed_y ? kFlagSeed : 0;
     if (P.seed_y) P.seed_d[s] = D;
     P.state[s] = SLOT_ACTIVE;
@@ -679,7 +711,7 @@ __device__ inline int item_slot(const Problem &P, int w) {
 // Work item r of slot s: split the selected leaf into its four children.
 // tab: the table of the slot's parameter row (LDS or global memory).
 template <int L, int GRAM>
-__device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int s, int r,
+__device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, const int *podd, int s, int r,
                         const double *tab) {
   const Ctr C = P.ctr[P.cid[s]];
   const Entry E = P.entries[C.entry];
@@ -727,7 +759,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, int 
       wave_sync();
       continue;
     }
-    eval_rect<L, GRAM>(S, P, pidmap, kNX, cx, cy, fa);
+    eval_rect<L, GRAM>(S, P, pidmap, podd, kNX, cx, cy, fa);
     dkey += store_region<L>(S, P, s, ri, cc);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
@@ -788,7 +820,7 @@ __device__ inline const Problem &kernarg_problem(const Problem &P) {
 template <int L, int GRAM>
 __global__ void __launch_bounds__(256) k_children(Problem P) {
   extern __shared__ double lds_raw[];
-  __shared__ int pidmap[Dims<L>::MU];
+  __shared__ int pidmap[Dims<L>::MU], podd[Dims<L>::MU];
   double *tabl = lds_raw;
   // the wave index is uniform in a wave: keep it (and all per-item
   // bookkeeping derived from it) in scalar registers
@@ -816,7 +848,7 @@ __global__ void __launch_bounds__(256) k_children(Problem P) {
     i1 = min(i0 + per, total);
   }
   if (i0 >= i1) return;  // uniform in the workgroup
-  build_pidmap<L>(pidmap, threadIdx.x, blockDim.x);
+  build_pidmap<L>(pidmap, podd, threadIdx.x, blockDim.x);
   int s = item_slot(P, i0), lo = P.woff[s], hi = P.woff[s + 1];  // current slot, its items
   int w = i0 + wv, seg = i0, loaded = -1;
 #pragma unroll 1
@@ -847,7 +879,7 @@ __global__ void __launch_bounds__(256) k_children(Problem P) {
         lo = P.woff[s];
         hi = P.woff[s + 1];
       }
-      do_item<L, GRAM>(S, kernarg_problem(P), pidmap, s, w - lo, tabl);
+      do_item<L, GRAM>(S, kernarg_problem(P), pidmap, podd, s, w - lo, tabl);
     }
     // the next segment starts at slot t (its first item is seg_hi)
     seg = seg_hi;
@@ -881,7 +913,8 @@ hipError_t launch_root_t(const Problem &p, hipStream_t s) {
 template <int L>
 size_t eval_lds_t(const Problem &p, int *waves_out, int *wave_doubles_out) {
   const size_t wave_b = sizeof(double) * wave_lds_doubles<L>(p.ff_identity);
-  const size_t tab_b = sizeof(double) * (size_t)p.tab_rows * kTabStride, fixed = 2048;
+  // fixed: the kernel's static LDS (two int tables over the form-factor pairs)
+  const size_t tab_b = sizeof(double) * (size_t)p.tab_rows * kTabStride, fixed = 4096;
   size_t budget = 65536;
   if (tab_b + wave_b + fixed > budget) budget = p.lds_limit > 0 ? (size_t)p.lds_limit : 65536;
   if (tab_b + wave_b + fixed > budget) return 0;

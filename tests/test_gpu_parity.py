@@ -334,6 +334,71 @@ def test_full_size_workload_sampled(P):
         assert np.array_equal(out, np.swapaxes(out, -1, -2))
 
 
+# ------------------------------------------------------------------ half-zone mode
+@pytest.mark.parametrize("gram", ["separable", "mfma"])
+def test_half_zone_mode_matches_the_oracle(P, gram):
+    """symmetry = 1 integrates p_y >= 0 only and weights each box pair by its
+    parity (0 or 2).  On C1 (FF5: s, extended s, d and the two p-waves, which
+    are odd) every integral is within the gate of the full-zone oracle, the
+    pairs of odd joint parity are exactly zero, and the trees hold about half
+    the leaves of the full-zone run."""
+    cfg = W.config("C1")
+    picks = W.containers(cfg)
+    ref = oracle_refs(cfg, picks, 1e-10)
+    g = P.GRAM_SEPARABLE if gram == "separable" else P.GRAM_MFMA
+    res = {}
+    for sym in (0, 1):
+        with P.Context(max_regions=1 << 16, max_active=512, gram=g, symmetry=sym) as c:
+            res[sym] = c.integrate(cfg["params"], cfg["q"], cfg["ff"], cfg["L"], rtol=1e-6)
+    out, _, st, rc = res[1]
+    assert rc == P.OK and st["not_converged"] == 0
+    for k, (ip, iq, ch) in enumerate(picks):
+        assert gate_ratio(out[ip, iq, ch], ref[k], 1e-6) <= 1.0, (ip, iq, ch)
+    assert np.all(out[..., :3, 3:] == 0.0) and np.all(out[..., 3:, :3] == 0.0)
+    assert np.array_equal(out, np.swapaxes(out, -1, -2))
+    print(f"half zone: {st['regions']} leaves against {res[0][2]['regions']} on the full zone")
+    assert st["regions"] < 0.6 * res[0][2]["regions"]
+
+
+@pytest.mark.parametrize("mode", ["per_integral", "weighted"])
+def test_half_zone_mode_with_other_error_tests(P, mode):
+    """the half-zone mode under the per-integral and the weighted tests, with
+    the 25-function box set (odd pairs: one of the two functions has an odd
+    number of sine factors)"""
+    row = [1.0, -0.25, -0.95, 0.05, 0.2]
+    q = np.array([[2.88, 0.26], [1.57, 1.31], [0.0, 0.0]])
+    ff, L = W.ff_box(2), 2
+    cfg = dict(params=np.array([row]), q=q, ff=ff, L=L)
+    picks = [(0, iq, ch) for iq in range(3) for ch in (O.PP, O.PH)]
+    ref = oracle_refs(cfg, picks, 1e-9)
+    em = P.ERR_PER_INTEGRAL if mode == "per_integral" else P.ERR_WEIGHTED
+    with P.Context(max_regions=1 << 16, err_mode=em, symmetry=1) as c:
+        if mode == "weighted":
+            # w_pp = 1, w_pq = 1/2: the global test's weights
+            c.set_pair_weights(np.broadcast_to(np.full((25, 25), 0.5) + 0.5 * np.eye(25),
+                                               (6, 25, 25)).copy())
+        out, _, st, rc = c.integrate([row], q, ff, L, rtol=1e-6)
+    assert rc == P.OK and st["not_converged"] == 0
+    odd = np.array([(((a // 5) in (2, 4)) ^ ((a % 5) in (2, 4))) for a in range(25)])
+    mask = odd[:, None] ^ odd[None, :]
+    for k, (ip, iq, ch) in enumerate(picks):
+        assert gate_ratio(out[ip, iq, ch], ref[k], 1e-6) <= 1.0, (iq, ch)
+        assert np.all(out[ip, iq, ch][mask] == 0.0)
+
+
+def test_half_zone_mode_argument_checks(P):
+    with pytest.raises(P.PaidError):
+        P.Context(symmetry=2)
+    with pytest.raises(P.PaidError):
+        P.Context(kind=P.GAUSS, symmetry=1)
+    from paid_1610_09991_amd import seed_model as SM
+    w, meta = SM.load()
+    with P.Context(symmetry=1) as c:
+        c.set_seed_model(w, kappa=meta["kappa"])
+        with pytest.raises(P.PaidError):
+            c.integrate([[1.0, -0.25, -0.95, 0.05, 0.2]], [[0.3, 0.2]], W.ff_box(1), 1)
+
+
 # ------------------------------------------------------------------ reduced precision
 # The dense Gram in FP32 or with three-term bf16 splits (FP32 accumulation)
 # carries ~2^-24 relative error per product; region sums, the error estimate
