@@ -20,7 +20,7 @@ namespace paid {
 namespace {
 
 constexpr int kBins = 512;
-constexpr int kSelThreads = 256;
+constexpr int kSelThreads = 512;
 // region codes hold ix and iy in 28 bits each: a rectangle of depth 28 (side
 // 2 pi / 2^28) is the smallest one a code can hold and is never split
 constexpr int kMaxDepth = 28;
