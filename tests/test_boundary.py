@@ -37,3 +37,15 @@ def test_binding_refuses_to_run_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(P, "_lib", None)
     with pytest.raises(RuntimeError):
         P.Context()
+
+
+def test_create_without_a_device_reports_it():
+    """on a host without a GPU the library refuses a context with PAID_EDEVICE
+    and a message, and runs nothing on the CPU in its place"""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    import paid_1610_09991_amd as P
+    with pytest.raises(P.PaidError) as ei:
+        P.Context()
+    assert ei.value.code == P.EDEVICE and "device" in str(ei.value)
