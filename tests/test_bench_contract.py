@@ -30,3 +30,13 @@ def test_shipped_launch_profile_is_complete():
         cfg = json.load(f)["config"]
     assert set(cfg) == {"batch", "batch_max", "max_active", "eval_wg_per_cu"}
     assert 1 <= cfg["batch"] <= cfg["batch_max"]
+
+
+def test_half_zone_variant_counts_only_computed_pairs():
+    """the survey's integral count: pairs zero by the inversion symmetry are not
+    computed in the half-zone mode and are not counted (20 of 45 for the 9-box
+    set, 6 of 15 for the 5-function set, 156 of 325 for the 25-box set)"""
+    import workloads as W
+    assert bench.computed_pairs(W.config("C2")["ff"], 1) == 25
+    assert bench.computed_pairs(W.config("C1")["ff"], 1) == 9
+    assert bench.computed_pairs(W.config("C4")["ff"], 2) == 169
