@@ -33,10 +33,12 @@ constexpr int kMaxMU = kMaxMB * (kMaxMB + 1) / 2;
 // singularity, which makes degree 13 exact to rounding on the interval (and
 // accurate out to 1.5 half-widths, where the divided difference of two close
 // energies is formed on the polynomial of one of them).
-// Row layout: c, 1/h, coef[14] of P(t) = S(c + h t), two doubles of padding
-// (a 144-byte stride starts consecutive rows on different LDS banks).
+// Row layout: c, 1/h, coef[14] of P(t) = S(c + h t), one double of padding:
+// an odd stride in doubles (136 bytes) spreads the rows that the lanes of a
+// wave read at one coefficient over the LDS banks (18 and 20 doubles are
+// slower, 16 much slower).
 constexpr int kTabDeg = 13;
-constexpr int kTabStride = 18;                 // c, 1/h, coef[14], 2 pad (spreads rows over LDS banks)
+constexpr int kTabStride = 17;                 // c, 1/h, coef[14], 1 pad (odd: spreads rows over LDS banks)
 constexpr int kTabCoef = 2;                    // offset of the coefficients in a row
 constexpr int kTabCentral = 9;                 // central intervals
 constexpr int kTabPerOct = 8;                  // intervals per octave above |x| = w
