@@ -47,7 +47,7 @@ K_FLOPS_PER_NODE = 80
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
 TRAFFIC_BYTES_PER_ITEM = 2405
-TRAFFIC_SOURCES_SHA256 = "c27a0f6a86314d2e27cde593512bea1cab935574d9a0887f69f440c21931c176"
+TRAFFIC_SOURCES_SHA256 = "427d8ef565c45c266f72224038901d248a6bbe9e8152909aeb60288feb2cb491"
 
 
 def kernel_sources_sha256() -> str:
