@@ -304,7 +304,7 @@ int paid_contract(struct paid_ctx *ctx, int n_l, int M, const double *chi, const
  *   base  t, tp, mu, T of the parameter row (its Omega is ignored)
  *   q [n_q][2], ff, n_ff, ff_L: as for paid_integrate
  *   VP, VC, VD [n_q][n_ff][n_ff]; P, C, D [n_q][n_ff][n_ff] in: the state at
- *   omega0, out: at omega1.  Host pointers. */
+ *   omega0, out: at omega1.  Host pointers (device pointers: PAID_EINVAL). */
 typedef struct {
   double omega0, omega1;  /* > 0 */
   double rtol, atol;      /* step control: max |err| <= atol + rtol max |state| */

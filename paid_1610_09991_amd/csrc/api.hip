@@ -1195,6 +1195,9 @@ int paid_flow(paid_ctx *c, const paid_params *base, const double *q, int n_q, co
       !(o.rtol > 0 || o.atol > 0) || !(o.rtol_int > 0) || o.max_steps < 1)
     return fail(c, PAID_EINVAL, "bad flow options");
   if (c->cfg.kind != PAID_BUBBLE_DOT) return fail(c, PAID_EINVAL, "the flow needs kind PAID_BUBBLE_DOT");
+  for (const void *a : {(const void *)VP, (const void *)VC, (const void *)VD, (const void *)P,
+                        (const void *)C, (const void *)D})
+    if (is_device_ptr(a)) return fail(c, PAID_EINVAL, "the flow takes couplings and state in host memory");
   const int M = n_ff;
   const size_t nm = (size_t)n_q * M * M, ny = 3 * nm;  // state: P, C, D
   std::vector<double> y(ny), V(ny);

@@ -41,3 +41,25 @@ def test_flow_matches_bubble_differences():
     for got, s0, ref in ((Pf, S0[0], dP), (Cf, S0[1], dC), (Df, S0[2], dD)):
         scale = max(np.abs(ref).max(), np.abs(s0).max())
         assert np.abs((got - s0) - ref).max() <= 5e-7 * scale
+
+
+def test_flow_refuses_device_arrays():
+    """the flow keeps its state on the host: device pointers are PAID_EINVAL
+    (not a fault)"""
+    import ctypes as C
+    import torch
+    import paid_1610_09991_amd as P
+    cfg = W.config("C1")
+    M, nq = 5, 2
+    q = np.ascontiguousarray(cfg["q"][:nq])
+    ff = np.ascontiguousarray(cfg["ff"])
+    dev = [torch.zeros((nq, M, M), dtype=torch.float64, device="cuda") for _ in range(6)]
+    prm = P.params_array([(1.0, 0.0, 0.0, 0.1, 0.0)])
+    with P.Context() as ctx:
+        o = P.FlowOpts()
+        P.lib().paid_flow_opts_default(C.byref(o))
+        fs = P.FlowStats()
+        rc = P.lib().paid_flow(ctx.h, C.c_void_p(prm.ctypes.data), C.c_void_p(q.ctypes.data), nq,
+                               C.c_void_p(ff.ctypes.data), M, 1,
+                               *[C.c_void_p(t.data_ptr()) for t in dev], C.byref(o), C.byref(fs))
+    assert rc == P.EINVAL
