@@ -44,6 +44,8 @@ struct Dims {
   static constexpr int MB = NB * NB;            // box functions
   static constexpr int NP = NB * (NB + 1) / 2;  // products u_a u_c, a <= c
   static constexpr int MU = MB * (MB + 1) / 2;  // pairs of box functions
+  // the four children's x-sums fit in the storage of the integrand values
+  static constexpr bool XALL = 4 * 2 * NP * NP <= kNX * kNX;
 };
 
 // per-wave scratch in LDS.  Buffers of different phases share storage: the
@@ -58,6 +60,9 @@ struct WaveLds {
     double g[kNX * kNX];           // integrand at the shared nodes
     struct {
       double g2[NP * NP], g1[NP * NP];  // x-sums of one child (separable path)
+    };
+    struct {  // x-sums of all four children (where XALL)
+      double g2b[Dims<L>::XALL ? 4 : 1][NP * NP], g1b[Dims<L>::XALL ? 4 : 1][NP * NP];
     };
   };
   union {
@@ -233,13 +238,18 @@ __device__ void sep_stage1(WaveLds<L> &S, int nco, int nrow) {
 
 // Stage 2 for child (cx, cy), then the form-factor pairs (identity basis) or
 // the full box Gram (general sets) scaled by the area factor fa.
+// the four children's x-sums in one pass over the lanes (where they fit:
+// 144 tasks in 3 passes instead of 36 in each of 4)
 template <int L>
-__device__ void sep_stage2(WaveLds<L> &S, const Problem &P, const int *pidmap, const int *podd,
-                           int cx, int cy, double fa) {
-  constexpr int NB = Dims<L>::NB, NP = Dims<L>::NP, MB = Dims<L>::MB, MU = Dims<L>::MU;
+constexpr bool kXsumsAll = Dims<L>::XALL;
+
+template <int L>
+__device__ void sep_xsums_all(WaveLds<L> &S) {
+  constexpr int NP = Dims<L>::NP;
   const int lane = lane_id();
-  for (int idx = lane; idx < NP * NP; idx += 64) {
-    int j = idx / NP, k = idx - j * NP;
+  for (int idx = lane; idx < 4 * NP * NP; idx += 64) {
+    const int ch = idx / (NP * NP), r = idx - ch * (NP * NP), cx = ch & 1, cy = ch >> 1;
+    const int j = r / NP, k = r - j * NP;
     double s2 = 0.0, s1 = 0.0;
 #pragma unroll
     for (int a = 0; a < kNF; ++a) {
@@ -248,26 +258,58 @@ __device__ void sep_stage2(WaveLds<L> &S, const Problem &P, const int *pidmap, c
       s2 = fma(c_rule.w2[a] * pj, S.h2[cy][x][k], s2);
       if (!(a & 1)) s1 = fma(c_rule.w1[a >> 1] * pj, S.h1[cy][x >> 1][k], s1);
     }
-    S.g2[idx] = s2;
-    S.g1[idx] = s1;
+    S.g2b[ch][r] = s2;
+    S.g1b[ch][r] = s1;
   }
   wave_sync();
+}
+
+template <int L>
+__device__ void sep_stage2(WaveLds<L> &S, const Problem &P, const int *pidmap, const int *podd,
+                           int cx, int cy, double fa, bool xsums_done) {
+  constexpr int NB = Dims<L>::NB, NP = Dims<L>::NP, MB = Dims<L>::MB, MU = Dims<L>::MU;
+  const int lane = lane_id();
+  const double *G2 = S.g2, *G1 = S.g1;
+  bool done = false;
+  if constexpr (kXsumsAll<L>) {
+    if (xsums_done) {
+      G2 = S.g2b[2 * cy + cx];
+      G1 = S.g1b[2 * cy + cx];
+      done = true;
+    }
+  }
+  if (!done) {
+    for (int idx = lane; idx < NP * NP; idx += 64) {
+      int j = idx / NP, k = idx - j * NP;
+      double s2 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int a = 0; a < kNF; ++a) {
+        int x = 8 * cx + a;
+        double pj = S.pp[0][x][j];
+        s2 = fma(c_rule.w2[a] * pj, S.h2[cy][x][k], s2);
+        if (!(a & 1)) s1 = fma(c_rule.w1[a >> 1] * pj, S.h1[cy][x >> 1][k], s1);
+      }
+      S.g2[idx] = s2;
+      S.g1[idx] = s1;
+    }
+    wave_sync();
+  }
   if (P.ff_identity) {
     for (int pid = lane; pid < MU; pid += 64) {
       int jk = pidmap[pid];
-      double q2 = S.g2[jk], f = fa;
+      double q2 = G2[jk], f = fa;
       if (P.sym) f = podd[pid] ? 0.0 : 2.0 * fa;
       S.cq[pid] = f * q2;
-      S.ce[pid] = f * (q2 - S.g1[jk]);
+      S.ce[pid] = f * (q2 - G1[jk]);
     }
   } else {
     for (int idx = lane; idx < MB * MB; idx += 64) {
       int m = idx / MB, n = idx - m * MB;
       int jk = prod_index<NB>(m / NB, n / NB) * NP + prod_index<NB>(m % NB, n % NB);
-      double q2 = S.g2[jk], f = fa;
+      double q2 = G2[jk], f = fa;
       if (P.sym) f = half_zone_factor<NB>(m, n) * fa;
       S.tq[idx] = f * q2;
-      S.ts[idx] = f * (q2 - S.g1[jk]);
+      S.ts[idx] = f * (q2 - G1[jk]);
     }
   }
   wave_sync();
@@ -523,9 +565,9 @@ constexpr int kSep = 3;
 
 template <int L, int GRAM>
 __device__ void eval_rect(WaveLds<L> &S, const Problem &P, const int *pidmap, const int *podd,
-                          int nco, int cx, int cy, double fa) {
+                          int nco, int cx, int cy, double fa, bool xsums_done = false) {
   if (GRAM == kSep) {
-    sep_stage2<L>(S, P, pidmap, podd, cx, cy, fa);
+    sep_stage2<L>(S, P, pidmap, podd, cx, cy, fa, xsums_done);
   } else {
     gram_mfma<L, GRAM>(S, P, nco, 8 * cx, 8 * cy, fa);
   }
@@ -746,6 +788,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
   if (skip != 15) {
     fill_nodes<L>(S, P, C, E, tab, kNX, x0, y0, wdt);
     if (GRAM == kSep) sep_stage1<L>(S, kNX, 2);
+    if constexpr (GRAM == kSep && kXsumsAll<L>) sep_xsums_all<L>(S);
   }
   const double fa = (0.25 * wdt) * (0.25 * wdt) / (4.0 * kPi * kPi);
   double dkey = -pkey;
@@ -759,7 +802,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
       wave_sync();
       continue;
     }
-    eval_rect<L, GRAM>(S, P, pidmap, podd, kNX, cx, cy, fa);
+    eval_rect<L, GRAM>(S, P, pidmap, podd, kNX, cx, cy, fa, true);
     dkey += store_region<L>(S, P, s, ri, cc);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
