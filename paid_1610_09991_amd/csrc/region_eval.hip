@@ -802,6 +802,38 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
       wave_sync();
       continue;
     }
+    if constexpr (GRAM == kSep && kXsumsAll<L>) {
+      if (P.ff_identity) {
+        // box-basis pairs straight from the x-sums into the child's record
+        // and the parent's delta, without staging them in LDS
+        const double *G2 = S.g2b[ch], *G1 = S.g1b[ch];
+        const long base = (long)s * P.cap + ri;
+        double part = 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+          const int pid = lane + 64 * k;
+          if (pid < MU) {
+            const int jk = pidmap[pid];
+            double f = fa;
+            if (P.sym) f = podd[pid] ? 0.0 : 2.0 * fa;
+            const double q2 = G2[jk], q = f * q2, e = fabs(f * (q2 - G1[jk]));
+            P.Q[base * MU + pid] = q;
+            if (P.E) P.E[base * MU + pid] = (float)e;
+            part += (P.err_mode != 0) ? e * (double)P.itau[(long)s * MU + pid] : e;
+            dv[k] += q;
+            dp[k] += (double)(float)e;
+          }
+        }
+        const double key = wave_sum(part);
+        if (lane == 0) {
+          P.key[base] = key;
+          P.code[base] = cc;
+        }
+        dkey += key;
+        wave_sync();
+        continue;
+      }
+    }
     eval_rect<L, GRAM>(S, P, pidmap, podd, kNX, cx, cy, fa, true);
     dkey += store_region<L>(S, P, s, ri, cc);
 #pragma unroll
