@@ -46,8 +46,8 @@ K_FLOPS_PER_NODE = 80
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2406
-TRAFFIC_SOURCES_SHA256 = "9e382878c3c3f9f308cffae5b4a9dc8a42e3f3d34ec54bf5bf42af3fbeb55a96"
+TRAFFIC_BYTES_PER_ITEM = 2408
+TRAFFIC_SOURCES_SHA256 = "7ffd60bea8fc858fe46ca4284e47cb3713395a1311e507767aaf6400cc6d4bad"
 
 
 def kernel_sources_sha256() -> str:
