@@ -531,9 +531,31 @@ __device__ void transform_ff(WaveLds<L> &S, const Problem &P) {
   }
 }
 
+// a double moved between lanes by a DPP pattern (both halves; VALU, no LDS)
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the 64 lanes in a fixed order, the same in every lane: within
+// each row of 16 lanes by DPP exchanges (partners lane ^ 1, lane ^ 2, then
+// the mirror images within 8 and within 16 lanes; a + b = b + a exactly, so
+// partners agree), then the four row sums as (r0 + r1) + (r2 + r3)
 __device__ inline double wave_sum(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);  // fixed order
-  return v;
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // Store one evaluated rectangle (S.cq, S.ce) into pool slot `ri` of slot s,
