@@ -46,8 +46,8 @@ K_FLOPS_PER_NODE = 80
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2408
-TRAFFIC_SOURCES_SHA256 = "7ffd60bea8fc858fe46ca4284e47cb3713395a1311e507767aaf6400cc6d4bad"
+TRAFFIC_BYTES_PER_ITEM = 2415
+TRAFFIC_SOURCES_SHA256 = "ac0980e7a2750cae2315c75c352b771455325346aab971db78a13e3694ad7b2d"
 
 
 def kernel_sources_sha256() -> str:
