@@ -33,12 +33,13 @@ constexpr int kMaxMU = kMaxMB * (kMaxMB + 1) / 2;
 // singularity, which makes degree 13 exact to rounding on the interval (and
 // accurate out to 1.5 half-widths, where the divided difference of two close
 // energies is formed on the polynomial of one of them).
-// Row layout: c, 1/h, coef[14] of P(t) = S(c + h t), one double of padding:
-// an odd stride in doubles (136 bytes) spreads the rows that the lanes of a
-// wave read at one coefficient over the LDS banks (18 and 20 doubles are
-// slower, 16 much slower).
+// Row layout: -c/h, 1/h, coef[14] of P(t) = S(c + h t), one double of
+// padding.  c/h is an integer (2j in the centre, 17 + 2m in an octave), so
+// t = x/h - c/h is one fused multiply-add.  An odd stride in doubles (136
+// bytes) spreads the rows that the lanes of a wave read at one coefficient
+// over the LDS banks (18 and 20 doubles are slower, 16 much slower).
 constexpr int kTabDeg = 13;
-constexpr int kTabStride = 17;                 // c, 1/h, coef[14], 1 pad (odd: spreads rows over LDS banks)
+constexpr int kTabStride = 17;                 // -c/h, 1/h, coef[14], 1 pad (odd: spreads rows over LDS banks)
 constexpr int kTabCoef = 2;                    // offset of the coefficients in a row
 constexpr int kTabCentral = 9;                 // central intervals
 constexpr int kTabPerOct = 8;                  // intervals per octave above |x| = w
@@ -94,17 +95,27 @@ __host__ __device__ inline uint64_t code_iy(uint64_t c) { return c & 0xFFFFFFFul
 
 // ---------------------------------------------------------------------------
 // Frequency-sum table evaluation.
-// interval of |x| (no transcendental: exponent and top mantissa bits of |x|/w)
+// interval of |x| (no transcendental: exponent and top mantissa bits of |x|/w).
+// Both candidates are formed and one is selected, without a branch; for
+// v >= 1 the bits above the top three mantissa bits are (exponent << 3 | m).
 __device__ inline int tab_index(const Entry &e, double ax) {
   const float v = (float)(ax * e.inv_w);
-  int j;
-  if (v < 1.0f) {
-    j = (int)fmaf(v, 8.0f, 0.5f);
-  } else {
-    const unsigned int b = __float_as_uint(v);
-    j = kTabCentral + ((int)(b >> 23) - 127) * kTabPerOct + (int)((b >> 20) & 7u);
-  }
+  const int jc = (int)fmaf(fminf(v, 1.0f), 8.0f, 0.5f);
+  const int jo = kTabCentral - 127 * kTabPerOct + (int)(__float_as_uint(v) >> 20);
+  const int j = v < 1.0f ? jc : jo;
   return j < e.J - 1 ? j : e.J - 1;
+}
+
+// n / d for a normal, non-zero d: the hardware reciprocal estimate refined by
+// two Newton-Raphson steps, then one residual correction of the quotient
+// (Markstein's scheme); no scaling for extreme exponents, which the far
+// pairs (|d| >= 0.02 w) never reach.
+__device__ inline double div_nr(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  const double q = n * r;
+  return fma(fma(-d, q, n), r, q);
 }
 
 // kernel K_j(a, b): ph = S[a,b], pp = -S[a,-b], with x = a and y = b (ph) or
@@ -124,10 +135,11 @@ __device__ inline double K_eval(const Entry &e, const double *tab, int ch, doubl
   const double d = x - y;
   const bool close = d * d < kDdSwitch2 * (x * x + e.w * e.w);
   const double ay = fabs(y);
-  const double *rx = tab + tab_index(e, x) * kTabStride;
-  const double *ry = close ? rx : tab + tab_index(e, ay) * kTabStride;
-  const double tx = (x - rx[0]) * rx[1];
-  const double ty = ((close ? y : ay) - ry[0]) * ry[1];
+  // row offsets by 24-bit multiplies (full rate; the 32-bit one is not)
+  const double *rx = tab + __umul24(tab_index(e, x), kTabStride);
+  const double *ry = close ? rx : tab + __umul24(tab_index(e, ay), kTabStride);
+  const double tx = fma(x, rx[1], rx[0]);
+  const double ty = fma(close ? y : ay, ry[1], ry[0]);
   const double *cx = rx + kTabCoef, *cy = ry + kTabCoef;
   double q = cx[kTabDeg], py = cy[kTabDeg], r = 0.0;
 #pragma unroll
@@ -136,7 +148,7 @@ __device__ inline double K_eval(const Entry &e, const double *tab, int ch, doubl
     q = fma(q, tx, cx[k]);
     py = fma(py, ty, cy[k]);
   }
-  const double s = close ? r * rx[1] : (q - (y < 0.0 ? -py : py)) / d;
+  const double s = close ? r * rx[1] : div_nr(q - (y < 0.0 ? -py : py), d);
   return ch ? s : -s;
 }
 
