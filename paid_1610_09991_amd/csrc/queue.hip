@@ -25,31 +25,47 @@ constexpr int kSelThreads = 512;
 // 2 pi / 2^28) is the smallest one a code can hold and is never split
 constexpr int kMaxDepth = 28;
 
-__device__ inline double block_sum(double v, double *sh) {
-  // fixed-order reduction: deterministic for a fixed block size
-  const int t = threadIdx.x;
+// Block reductions over the pairwise tree that halves the block at every
+// level (t with t + o, o = blockDim/2, ..., 1), evaluated in that order: the
+// levels o >= 64 pair whole waves, so the first wave forms them per lane from
+// one LDS write of the block, and the levels o < 64 are a butterfly of lane
+// exchanges within it (lane t < o pairs with t + o, as in the tree).  Three
+// barriers instead of one per level; the result is bit-identical to the tree
+// for a fixed block size (a power of two, 64..1024).
+template <class Op>
+__device__ inline double block_tree(double v, double *sh, Op op) {
+  const int t = threadIdx.x, lane = t & 63, nw = blockDim.x >> 6;
   sh[t] = v;
   __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (t < o) sh[t] += sh[t + o];
-    __syncthreads();
+  if (t < 64) {
+    double x[16];
+#pragma unroll
+    for (int w = 0; w < 16; ++w) x[w] = w < nw ? sh[w * 64 + lane] : 0.0;
+#pragma unroll
+    for (int h = 8; h >= 1; h >>= 1)
+      if (h < nw)
+#pragma unroll
+        for (int w = 0; w < h; ++w) x[w] = op(x[w], x[w + h]);
+    double r = x[0];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double y = __shfl_xor(r, o, 64);
+      r = lane < o ? op(r, y) : op(y, r);
+    }
+    if (t == 0) sh[blockDim.x] = r;
   }
-  double r = sh[0];
+  __syncthreads();
+  const double r = sh[blockDim.x];
   __syncthreads();
   return r;
 }
 
+__device__ inline double block_sum(double v, double *sh) {
+  return block_tree(v, sh, [](double a, double b) { return a + b; });
+}
+
 __device__ inline double block_max(double v, double *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (t < o) sh[t] = fmax(sh[t], sh[t + o]);
-    __syncthreads();
-  }
-  double r = sh[0];
-  __syncthreads();
-  return r;
+  return block_tree(v, sh, [](double a, double b) { return fmax(a, b); });
 }
 
 // exclusive block prefix of an int flag/count; returns the block total
@@ -363,11 +379,17 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
   for (long b0 = 0; b0 < n; b0 += blockDim.x) {
     long i = b0 + t;
     int bin = (i < n) ? key_bin(P.key[base + i], eb) : kBins;
-    int isp = (i < n && bin == bpart) ? 1 : 0, ex1;
-    int totp = block_scan(isp, shi, ex1);
-    int flag = (i < n) && (bin <= bfull || (isp && seenpart + ex1 < part));
-    int ex2;
-    int totf = block_scan(flag, shi, ex2);
+    // one scan of both flags (16 bits each): the leaves of bin bpart are
+    // taken in index order while room is left, so the prefix of the taken
+    // ones follows from that of bin bpart's
+    const int isp = (i < n && bin == bpart) ? 1 : 0, full = (i < n && bin <= bfull) ? 1 : 0;
+    int ex;
+    const int tot = block_scan(isp | (full << 16), shi, ex);
+    const int ex1 = ex & 0xFFFF, totp = tot & 0xFFFF;
+    const int room = part - seenpart > 0 ? part - seenpart : 0;
+    const int flag = full || (isp && ex1 < room);
+    const int ex2 = (ex >> 16) + (ex1 < room ? ex1 : room);
+    const int totf = (tot >> 16) + (totp < room ? totp : room);
     if (flag && out + ex2 < s_k) sel[out + ex2] = (int)i;
     out += totf;
     seenpart += totp;
