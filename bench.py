@@ -46,7 +46,7 @@ K_FLOPS_PER_NODE = 80
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2415
+TRAFFIC_BYTES_PER_ITEM = 2416
 TRAFFIC_SOURCES_SHA256 = "ed6ac3d5f5a8c23fb8f124b476fbb5c2c1dfaff29bf849d92444f958632854f9"
 
 
