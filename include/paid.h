@@ -114,7 +114,9 @@ typedef struct {
                            compute unit (0: 16 per workgroup the kernel's
                            occupancy fits on a compute unit); the work items
                            of a round are split over them in geometrically
-                           shrinking ranges */
+                           shrinking ranges; grids much shorter than the
+                           default hand the first workgroups more than an
+                           even share (8 per occupancy slot: ~25% slower) */
   int symmetry;         /* 1: integrate over the half zone p_y >= 0 only.  The
                            integrand of both bubbles is even under p -> -p
                            (it swaps the energies eps(l/2 + p) and
