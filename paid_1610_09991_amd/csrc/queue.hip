@@ -31,7 +31,8 @@ constexpr int kMaxDepth = 28;
 // one LDS write of the block, and the levels o < 64 are a butterfly of lane
 // exchanges within it (lane t < o pairs with t + o, as in the tree).  Three
 // barriers instead of one per level; the result is bit-identical to the tree
-// for a fixed block size (a power of two, 64..1024).
+// for a fixed block size (a power of two, 64..1024).  sh holds blockDim + 1
+// doubles (the last one broadcasts the result).
 template <class Op>
 __device__ inline double block_tree(double v, double *sh, Op op) {
   const int t = threadIdx.x, lane = t & 63, nw = blockDim.x >> 6;
