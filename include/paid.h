@@ -260,6 +260,24 @@ int paid_mlp_forward(struct paid_ctx *ctx, const float *w, const float *x, int n
 int paid_mlp_loss_grad(struct paid_ctx *ctx, const float *w, const float *x, const float *y,
                        int n, float *grad, double *loss);
 
+/* The loss and gradient of paid_mlp_loss_grad for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid allocation.  Same kernels, same
+ * results (bit for bit) as paid_mlp_loss_grad, but no call allocates or
+ * frees memory: the working memory (per-sample activations and deltas of up
+ * to PAID_NOALLOC_MAX_N samples, and the loss; 13.6 MB) is a fixed array of
+ * the library on each device, held until the process ends, and the loss is
+ * read back through the context's pinned buffer.
+ *   w [nparams], x [n][7], y [n][256], grad [nparams]: device memory only
+ *   (host pointers: PAID_EINVAL); 1 <= n <= PAID_NOALLOC_MAX_N (larger n:
+ *   PAID_EINVAL, nothing launched); loss may be NULL.
+ * Every call on a device uses that device's one array: calls that overlap
+ * on one device (other contexts, other host threads) race and must be
+ * serialised by the caller.  Nothing in the array has to start at zero. */
+#define PAID_NOALLOC_MAX_N 2048
+int paid_mlp_loss_grad_noalloc(struct paid_ctx *ctx, const float *w, const float *x,
+                               const float *y, int n, float *grad, double *loss);
+
 /* One Adam step in place (beta1 0.9, beta2 0.999, eps 1e-8, step t >= 1):
  * m, v are the moment arrays, all [nparams], device memory only. */
 int paid_mlp_adam(struct paid_ctx *ctx, float *w, const float *grad, float *m, float *v, int t,

@@ -82,7 +82,10 @@ EXPORTS = ("paid_config_default", "paid_create", "paid_integrate", "paid_kernel_
            "paid_children_eval", "paid_destroy", "paid_last_error", "paid_mlp_nparams",
            "paid_set_seed_model", "paid_set_label_output", "paid_mlp_forward",
            "paid_mlp_loss_grad", "paid_mlp_adam", "paid_train_opts_default", "paid_seed_train",
-           "paid_contract", "paid_flow_opts_default", "paid_flow", "paid_set_pair_weights")
+           "paid_contract", "paid_flow_opts_default", "paid_flow", "paid_set_pair_weights",
+           "paid_mlp_loss_grad_noalloc")
+
+NOALLOC_MAX_N = 2048  # PAID_NOALLOC_MAX_N
 
 _lib = None
 
@@ -120,6 +123,7 @@ def lib():
         L.paid_set_pair_weights.argtypes = [vp, vp]
         L.paid_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
         L.paid_mlp_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int, vp, dp]
+        L.paid_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, vp, C.c_int, vp, dp]
         L.paid_mlp_adam.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_float]
         L.paid_train_opts_default.argtypes = [C.POINTER(TrainOpts)]
         L.paid_seed_train.argtypes = [vp, vp, vp, C.c_int, C.POINTER(TrainOpts), vp, vp]
@@ -278,6 +282,15 @@ class Context:
         self._check(lib().paid_mlp_loss_grad(self.h, _ptr(w), _ptr(x), _ptr(y), n, _ptr(grad),
                                              C.byref(loss)), allow_noconv=False)
         return loss.value, grad
+
+    def mlp_loss_grad_noalloc(self, w, x, y, grad):
+        """paid_mlp_loss_grad through the entry point that allocates nothing:
+        w, x, y, grad must be device tensors; returns the loss."""
+        loss = C.c_double(0.0)
+        self._check(lib().paid_mlp_loss_grad_noalloc(self.h, _ptr(w), _ptr(x), _ptr(y), x.shape[0],
+                                                     _ptr(grad), C.byref(loss)),
+                    allow_noconv=False)
+        return loss.value
 
     def mlp_adam(self, w, g, m, v, t, lr):
         """one Adam step in place on device tensors w, m, v"""

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -65,6 +66,7 @@ struct paid_ctx {
   int *host_counters = nullptr;  // pinned
   int max_J = 1;                 // rows of the largest table of the last build
   int lds_limit = 0;             // LDS bytes per workgroup (device attribute)
+  float *noalloc = nullptr;      // this device's fixed working memory (paid_mlp_loss_grad_noalloc)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profile: around the evaluation launch
 };
 
@@ -132,6 +134,25 @@ void cc_rule_ascending(int n, double *x, double *w) {
 }
 
 int g_rule_ready[64] = {0};
+
+// device address of each device's fixed working memory, looked up once per
+// device with that device current
+std::mutex g_noalloc_mu;
+float *g_noalloc_ptr[64] = {nullptr};
+
+int ensure_noalloc(paid_ctx *c) {
+  const int dev = c->cfg.device;
+  if (dev < 0 || dev >= 64) return fail(c, PAID_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    float *p = nullptr;
+    HIPCHK(c, noalloc_scratch_address(&p));
+    if (!p) return fail(c, PAID_EDEVICE, "no address for the fixed working memory");
+    g_noalloc_ptr[dev] = p;
+  }
+  c->noalloc = g_noalloc_ptr[dev];
+  return PAID_OK;
+}
 
 int ensure_rule(paid_ctx *c) {
   int dev = c->cfg.device;
@@ -396,6 +417,7 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
     }
   }
   int rc = ensure_rule(c);
+  if (rc == PAID_OK) rc = ensure_noalloc(c);
   if (rc != PAID_OK) {
     g_create_error = c->err;
     paid_destroy(c);
@@ -985,6 +1007,51 @@ int paid_mlp_forward(paid_ctx *c, const float *w, const float *x, int n, float *
   return PAID_OK;
 }
 
+// forward pass, mean squared error and backward pass on device arrays with
+// the per-sample buffers of a and the loss in dloss (shared by both entry
+// points)
+static hipError_t loss_grad_launch(paid_ctx *c, const float *dw, const float *dx, const float *dyl,
+                                   int n, MlpAct &a, float *yhat, float *dY, float *dg,
+                                   double *dloss) {
+  hipError_t e;
+  if ((e = mlp_forward(dw, dx, n, a, yhat, c->stream)) != hipSuccess) return e;
+  if ((e = mlp_mse(yhat, dyl, (long)n * kMlpOut, dY, dloss, nullptr, c->stream)) != hipSuccess) return e;
+  return mlp_backward(dw, dx, n, a, dY, dg, c->stream);
+}
+
+int paid_mlp_loss_grad_noalloc(paid_ctx *c, const float *w, const float *x, const float *y, int n,
+                               float *grad, double *loss) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if (!w || !x || !y || !grad || n < 1) return fail(c, PAID_EINVAL, "bad arguments");
+  if (n > kNoAllocMaxN)
+    return fail(c, PAID_EINVAL, "n = %d exceeds the fixed working memory (at most %d samples)", n,
+                kNoAllocMaxN);
+  if (!is_device_ptr(w) || !is_device_ptr(x) || !is_device_ptr(y) || !is_device_ptr(grad))
+    return fail(c, PAID_EINVAL, "paid_mlp_loss_grad_noalloc takes device arrays only");
+  if (!c->noalloc) return fail(c, PAID_EINTERNAL, "fixed working memory not set up");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  // carve the per-sample buffers of n samples and the loss from the array
+  const size_t h = (size_t)kMlpHid * n, o = (size_t)kMlpOut * n;
+  float *p = c->noalloc;
+  MlpAct a;
+  for (int l = 0; l < 3; ++l) {
+    a.Z[l] = p + (size_t)l * h;
+    a.A[l] = p + (size_t)(3 + l) * h;
+    a.D[l] = p + (size_t)(6 + l) * h;
+  }
+  a.Z[3] = nullptr;
+  float *yhat = p + 9 * h, *dY = yhat + o;
+  double *dloss = reinterpret_cast<double *>(p + kNoAllocActFloats);
+  HIPCHK(c, loss_grad_launch(c, w, x, y, n, a, yhat, dY, grad, dloss));
+  // the loss goes through the context's pinned buffer (bytes 32..39)
+  double *hl = reinterpret_cast<double *>(reinterpret_cast<char *>(c->host_counters) + 32);
+  HIPCHK(c, hipMemcpyAsync(hl, dloss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = *hl;
+  return PAID_OK;
+}
+
 int paid_mlp_loss_grad(paid_ctx *c, const float *w, const float *x, const float *y, int n,
                        float *grad, double *loss) {
   if (!c) return PAID_EINVAL;
@@ -1004,9 +1071,7 @@ int paid_mlp_loss_grad(paid_ctx *c, const float *w, const float *x, const float 
   float *yhat, *dY;
   if ((rc = carve_act(c, act, n, a, yhat, dY)) != PAID_OK) return rc;
   HIPCHK(c, tl.ensure(sizeof(double)));
-  HIPCHK(c, mlp_forward(dw, dx, n, a, yhat, c->stream));
-  HIPCHK(c, mlp_mse(yhat, dyl, (long)n * kMlpOut, dY, tl.as<double>(), nullptr, c->stream));
-  HIPCHK(c, mlp_backward(dw, dx, n, a, dY, dg, c->stream));
+  HIPCHK(c, loss_grad_launch(c, dw, dx, dyl, n, a, yhat, dY, dg, tl.as<double>()));
   if ((rc = finish_out(c, grad, dg, np)) != PAID_OK) return rc;
   double hl = 0.0;
   HIPCHK(c, hipMemcpyAsync(&hl, tl.p, sizeof(double), hipMemcpyDeviceToHost, c->stream));

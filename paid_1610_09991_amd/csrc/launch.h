@@ -178,6 +178,15 @@ hipError_t mlp_gather(const float *X, const float *Y, const int *idx, const int 
                       float *Xb, float *Yb, hipStream_t s);
 hipError_t mlp_count(int *c, hipStream_t s);
 
+// fixed working memory of paid_mlp_loss_grad_noalloc: per-sample buffers of
+// at most kNoAllocMaxN samples (9 x 128 + 2 x 256 floats each) and the loss
+// (two floats' room for one double, 256-byte aligned after the buffers)
+constexpr int kNoAllocMaxN = PAID_NOALLOC_MAX_N;
+constexpr long kNoAllocActFloats = (long)kNoAllocMaxN * (9 * kMlpHid + 2 * kMlpOut);
+constexpr long kNoAllocFloats = kNoAllocActFloats + 64;
+// device address of this device's copy of the array (call with the device current)
+hipError_t noalloc_scratch_address(float **ptr);
+
 // ------------------------------------------------------------------ contraction
 hipError_t launch_contract(int n_l, int M, const double *chi, const double *VP, const double *VC,
                            const double *VD, double *dP, double *dC, double *dD, hipStream_t s);

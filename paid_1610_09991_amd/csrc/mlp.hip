@@ -290,4 +290,22 @@ hipError_t mlp_count(int *c, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ fixed working memory
+// Working memory of the loss-and-gradient entry point that allocates
+// nothing: the per-sample buffers of kNoAllocMaxN samples (pre-activations,
+// activations, deltas, outputs, output deltas) and the FP64 loss.  Every
+// element a call reads is written earlier in the same call, so nothing has
+// to start at zero.  Each device holds its own copy of the array at its own
+// address; host code must use that address (from hipGetSymbolAddress), never
+// the array's name, which on the host is only a stand-in.
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+hipError_t noalloc_scratch_address(float **ptr) {
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  *ptr = static_cast<float *>(p);
+  return hipSuccess;
+}
+
 }  // namespace paid
