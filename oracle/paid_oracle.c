@@ -506,22 +506,38 @@ static double po_key(const po_options *o, int np, int pair, const double *err,
   return k;
 }
 
+/* leaves of the final tree (mode B): rectangles and Q_2N per pair, in
+   creation order, at most cap of them; *n receives the leaf count */
+typedef struct {
+  double *rects, *q2n;
+  long cap, *n;
+} po_leaf_out;
+
 static int po_integrate_impl(const po_problem *pr, const po_options *o, double *value,
-                             double *errout, po_stats *st, double *labels);
+                             double *errout, po_stats *st, double *labels,
+                             const po_leaf_out *lo);
 
 int po_integrate(const po_problem *pr, const po_options *o, double *value, double *errout,
                  po_stats *st) {
-  return po_integrate_impl(pr, o, value, errout, st, NULL);
+  return po_integrate_impl(pr, o, value, errout, st, NULL, NULL);
 }
 
 int po_integrate_labels(const po_problem *pr, const po_options *o, double *value, double *err,
                         po_stats *st, double labels[256]) {
   if (!labels || !o || o->mode != PO_MODE_B) return -2;
-  return po_integrate_impl(pr, o, value, err, st, labels);
+  return po_integrate_impl(pr, o, value, err, st, labels, NULL);
+}
+
+int po_integrate_leaves(const po_problem *pr, const po_options *o, double *value, double *err,
+                        po_stats *st, double *rects, double *q2n, long cap, long *n_leaves) {
+  if (!o || o->mode != PO_MODE_B || !n_leaves || cap < 0) return -2;
+  po_leaf_out lo = {rects, q2n, cap, n_leaves};
+  return po_integrate_impl(pr, o, value, err, st, NULL, &lo);
 }
 
 static int po_integrate_impl(const po_problem *pr, const po_options *o, double *value,
-                             double *errout, po_stats *st, double *labels) {
+                             double *errout, po_stats *st, double *labels,
+                             const po_leaf_out *lo) {
   if (!pr || !o || !value || o->batch < 1 || !(o->rtol >= 0) || !(o->atol >= 0) ||
       (o->rtol <= 0 && o->atol <= 0) || o->max_regions < 1)
     return -2;
@@ -655,6 +671,18 @@ static int po_integrate_impl(const po_problem *pr, const po_options *o, double *
       if (s.leaf[i]) memcpy(&rl[4 * nl++], &s.geo[4 * i], 4 * sizeof(double));
     po_tree_labels(rl, nl, labels);
     free(rl);
+  }
+  if (lo) {
+    long nl = 0;
+    for (long i = 0; i < s.n; ++i) {
+      if (!s.leaf[i]) continue;
+      if (nl < lo->cap) {
+        if (lo->rects) memcpy(&lo->rects[4 * nl], &s.geo[4 * i], 4 * sizeof(double));
+        if (lo->q2n) memcpy(&lo->q2n[nl * MU], &s.q2n[i * MU], MU * sizeof(double));
+      }
+      ++nl;
+    }
+    *lo->n = nl;
   }
   rc = S.converged ? 0 : 1;
 done:

@@ -95,6 +95,12 @@ int po_region_eval(const po_problem *pr, int N, double x0, double x1, double y0,
    Returns 0 on convergence, 1 if max_regions was hit, <0 on bad input. */
 int po_integrate(const po_problem *pr, const po_options *opt, double *value,
                  double *err, po_stats *st);
+/* po_integrate in mode B that also returns the leaves of the final tree in
+   creation order: rects [cap][4] = (x0, x1, y0, y1) and q2n [cap][n_ff (n_ff+1)/2]
+   (either may be NULL), the first cap of them; *n_leaves = their number. */
+int po_integrate_leaves(const po_problem *pr, const po_options *opt, double *value,
+                        double *err, po_stats *st, double *rects, double *q2n, long cap,
+                        long *n_leaves);
 /* Many problems, OpenMP over problems when nthreads > 1. Returns the number
    of problems that did not converge, or <0 on bad input. */
 int po_integrate_batch(const po_problem *prs, int n, const po_options *opt,

@@ -228,3 +228,37 @@ def test_weighted_criterion_holds_against_a_tight_reference():
         assert err <= 1e-6 * np.sum(pw * np.abs(ref[iu]))
     _, _, sg = _wcont(None).integrate(rtol=1e-6, err_mode=O.ERR_GLOBAL, batch=4)
     assert st["regions"] < sg["regions"]
+
+
+def test_oracle_leaves_tile_the_zone_and_sum_to_the_value(oracle_lib):
+    """the leaves the oracle returns (mode B, MaxTask 1) cover the zone once
+    (their areas add up to (2 pi)^2 and none overlaps another), their number
+    is the leaf count of the statistics, each leaf's Q_2N is the rule applied
+    to its rectangle, and their sum in creation order is the returned value"""
+    O = oracle_lib
+    ff = np.eye(9)
+    c = O.Container(ff, 1, t=1.0, tp=-0.25, mu=-0.95, T=0.1, Omega=0.3, lx=1.07, ly=-2.31,
+                    channel=O.PP)
+    v, e, st, rects, q2n = c.integrate_leaves(rtol=1e-3)
+    assert len(rects) == st["regions"] > 4
+    w = rects[:, 1] - rects[:, 0]
+    assert np.allclose(w, rects[:, 3] - rects[:, 2])
+    assert abs(np.sum(w * w) - (2 * np.pi) ** 2) <= 1e-12
+    # no overlap: leaves are quadtree cells, so two overlap only if one contains the other
+    lo = np.round((rects[:, [0, 2]] + np.pi) / w[:, None]).astype(np.int64)
+    d = np.round(np.log2(2 * np.pi / w)).astype(int)
+    cells = set()
+    for (ix, iy), dd in zip(lo, d):
+        for a in range(dd + 1):
+            anc = (a, ix >> (dd - a), iy >> (dd - a))
+            assert anc not in cells or a == dd, "a leaf lies inside another leaf"
+        cells.add((dd, ix, iy))
+    assert len(cells) == len(rects)
+    for k in (0, len(rects) // 2, len(rects) - 1):
+        _, q = c.region(*rects[k])
+        assert np.array_equal(q, q2n[k])
+    iu = np.triu_indices(9)
+    s = np.zeros(45)
+    for row in q2n:
+        s += row
+    assert np.array_equal(s, v[iu])
