@@ -92,7 +92,10 @@ typedef struct {
   int device;           /* HIP device ordinal */
   int N;                /* coarse rule: N intervals per axis (fine: 2N); 4 */
   int batch;            /* minimum leaves split per container per round
-                           (the MaxTask analogue), >= 1 */
+                           (the MaxTask analogue), >= 1; batch = batch_max
+                           = 1 splits exactly the leaf of largest key per
+                           round, ties by creation order (the serial order
+                           of Alg. 2) */
   int batch_max;        /* maximum leaves split per container per round */
   int err_mode;         /* PAID_ERR_* */
   int precision;        /* PAID_FP64 / PAID_FP32 / PAID_BF16X3 */
@@ -126,6 +129,13 @@ typedef struct {
                            and any other pair to twice its half-zone
                            integral.  Not part of the paper's scheme; not
                            with PAID_GAUSS, learned seeding or tree labels */
+  int eval_layout;      /* region-evaluation kernel: 0 (default) the fastest for
+                           the basis (for the 9-function box basis with the
+                           separable projection over the full zone, two lanes
+                           per child rectangle and 8 parents per wave, all
+                           sums in registers; otherwise one wave per parent),
+                           1 always one wave per parent.  Both compute the same
+                           rule sums, in different rounding orders */
 } paid_config;
 
 /* one parameter row: dispersion, temperature and flow scale */
@@ -251,6 +261,18 @@ int paid_set_label_output(struct paid_ctx *ctx, float *features, float *labels);
  * w_pq = (sum_m |V_mp|)(sum_n |V_qn|), sum_mn |dX_mn| <= sum w |d chi|).
  * Host or device pointer, caller-owned and sized for each call; NULL clears. */
 int paid_set_pair_weights(struct paid_ctx *ctx, const double *w);
+
+/* Make every later paid_integrate call on ctx also write, per container in
+ * the order of `out`, the leaves of its final tree in the library's pool
+ * order, at most cap of them: codes [n_ctr][cap][3] = (depth, ix, iy) of the
+ * rectangle x in [-pi + 2pi ix/2^depth, -pi + 2pi (ix+1)/2^depth), likewise
+ * y (entries past the last leaf are -1), and q2n [n_ctr][cap][n_ff (n_ff+1)/2]
+ * the rectangle's Q_2N for the pairs p <= q.  Caller-owned, sized for each
+ * call, host or device; NULLs turn it off.  With batch = batch_max = 1 every
+ * round splits the leaf of largest key (ties by creation order), which is
+ * the serial order of Alg. 2, so the leaves can be compared one by one with
+ * a serial implementation. */
+int paid_set_leaf_output(struct paid_ctx *ctx, int *codes, double *q2n, long cap);
 
 /* Model forward pass: x [n][7] -> y [n][256]. */
 int paid_mlp_forward(struct paid_ctx *ctx, const float *w, const float *x, int n, float *y);

@@ -38,7 +38,8 @@ class Config(C.Structure):
                 ("kind", C.c_int), ("nu", C.c_double), ("max_regions", C.c_long),
                 ("max_active", C.c_int), ("pool_gib", C.c_double),
                 ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int),
-                ("graph", C.c_int), ("eval_wg_per_cu", C.c_int), ("symmetry", C.c_int)]
+                ("graph", C.c_int), ("eval_wg_per_cu", C.c_int), ("symmetry", C.c_int),
+                ("eval_layout", C.c_int)]
 
 
 class Params(C.Structure):
@@ -83,7 +84,7 @@ EXPORTS = ("paid_config_default", "paid_create", "paid_integrate", "paid_kernel_
            "paid_set_seed_model", "paid_set_label_output", "paid_mlp_forward",
            "paid_mlp_loss_grad", "paid_mlp_adam", "paid_train_opts_default", "paid_seed_train",
            "paid_contract", "paid_flow_opts_default", "paid_flow", "paid_set_pair_weights",
-           "paid_mlp_loss_grad_noalloc")
+           "paid_mlp_loss_grad_noalloc", "paid_set_leaf_output")
 
 NOALLOC_MAX_N = 2048  # PAID_NOALLOC_MAX_N
 
@@ -121,6 +122,7 @@ def lib():
         L.paid_set_seed_model.argtypes = [vp, vp, C.c_int, C.c_double]
         L.paid_set_label_output.argtypes = [vp, vp, vp]
         L.paid_set_pair_weights.argtypes = [vp, vp]
+        L.paid_set_leaf_output.argtypes = [vp, vp, vp, C.c_long]
         L.paid_mlp_forward.argtypes = [vp, vp, vp, C.c_int, vp]
         L.paid_mlp_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int, vp, dp]
         L.paid_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, vp, C.c_int, vp, dp]
@@ -257,6 +259,15 @@ class Context:
         self._pw = None if w is None else (w if hasattr(w, "data_ptr") else _f64(w))
         self._check(lib().paid_set_pair_weights(self.h, _ptr(self._pw) if w is not None else None),
                     allow_noconv=False)
+
+    def set_leaf_output(self, codes=None, q2n=None):
+        """Arm the leaf output of later integrate() calls: codes [n_ctr][cap][3]
+        int32 and q2n [n_ctr][cap][MU] float64 (kept alive here; None clears)."""
+        self._leaves = (codes, q2n)
+        cap = 0 if codes is None else codes.shape[1]
+        self._check(lib().paid_set_leaf_output(
+            self.h, _ptr(codes) if codes is not None else None,
+            _ptr(q2n) if q2n is not None else None, cap), allow_noconv=False)
 
     def set_label_output(self, features=None, labels=None):
         """Arm per-container features [n][7] and tree labels [n][256] (FP32

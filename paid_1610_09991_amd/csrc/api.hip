@@ -63,6 +63,13 @@ struct paid_ctx {
   float *feat_out = nullptr, *lab_out = nullptr;
   const double *pair_w = nullptr;  // weighted mode: caller's [n_ctr][M][M]
   DevBuf pairw;
+  // lockstep mode (batch = batch_max = 1): creation index of every leaf
+  DevBuf born;
+  // leaf output of finished containers
+  int *leaf_codes = nullptr;
+  double *leaf_q = nullptr;
+  long leaf_cap = 0;
+  DevBuf lcodes, lq;
   int *host_counters = nullptr;  // pinned
   int max_J = 1;                 // rows of the largest table of the last build
   int lds_limit = 0;             // LDS bytes per workgroup (device attribute)
@@ -103,6 +110,8 @@ bool is_device_ptr(const void *p) {
   }
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
+
+constexpr double kPiH = 3.14159265358979323846;
 
 // Clenshaw-Curtis rule with n intervals on [-1,1], ascending nodes; weights
 // from the moment conditions sum_k w_k T_j(x_k) = int_{-1}^{1} T_j, j = 0..n,
@@ -161,12 +170,16 @@ int ensure_rule(paid_ctx *c) {
   double x1[kNCo];
   cc_rule_ascending(kNF - 1, rc.xi, rc.w2);
   cc_rule_ascending(kNCo - 1, x1, rc.w1);
+  for (int d = 0; d < kDelDepths; ++d)
+    for (int a = 0; a < 5; ++a) {
+      const double del = ldexp(kPiH, -(d + 1)) * rc.xi[a];
+      rc.cdel[d][a] = cos(del);
+      rc.sdel[d][a] = sin(del);
+    }
   HIPCHK(c, set_rule_constants(rc));
   if (dev >= 0 && dev < 64) g_rule_ready[dev] = 1;
   return PAID_OK;
 }
-
-constexpr double kPiH = 3.14159265358979323846;
 
 // host bookkeeping of one parameter row's table (sizes only; the table
 // itself is computed on the device)
@@ -385,6 +398,7 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
   if (cfg.eval_wg_per_cu < 0 || cfg.eval_wg_per_cu > 1024)
     return fail(nullptr, PAID_EINVAL, "eval_wg_per_cu must be 0..1024");
   if (cfg.symmetry != 0 && cfg.symmetry != 1) return fail(nullptr, PAID_EINVAL, "symmetry must be 0 or 1");
+  if (cfg.eval_layout != 0 && cfg.eval_layout != 1) return fail(nullptr, PAID_EINVAL, "eval_layout must be 0 or 1");
   if (cfg.symmetry && cfg.kind == PAID_GAUSS)
     return fail(nullptr, PAID_EINVAL, "the Gaussian test integrand is not even under p -> -p");
   int ndev = 0;
@@ -436,7 +450,8 @@ void paid_destroy(paid_ctx *c) {
                     &c->slot_d,  &c->sel,  &c->dv,    &c->de,    &c->dep,   &c->itau,
                     &c->errp,    &c->stl,  &c->counters, &c->outs, &c->errs,
                     &c->seedw,   &c->sfeat, &c->sfold, &c->sy,  &c->sact,  &c->pyr,
-                    &c->seedd,   &c->ifill, &c->labtmp, &c->pairw};
+                    &c->seedd,   &c->ifill, &c->labtmp, &c->pairw, &c->born, &c->lcodes,
+                    &c->lq};
   for (DevBuf *b : bufs) b->release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -524,6 +539,8 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   if (store_E) HIPCHK(c, c->dep.ensure(sizeof(double) * W * (size_t)bmax * MU));
   HIPCHK(c, c->stl.ensure(sizeof(long) * 3 * W));
   HIPCHK(c, c->ifill.ensure(sizeof(int) * W * (size_t)bmax));
+  const bool lockstep = bmin == 1 && bmax == 1;
+  if (lockstep) HIPCHK(c, c->born.ensure(sizeof(unsigned int) * W * (size_t)cap));
   HIPCHK(c, c->counters.ensure(256));
   const bool out_dev = is_device_ptr(out), err_dev = err_out && is_device_ptr(err_out);
   const size_t out_bytes = sizeof(double) * (size_t)n_ctr * M * M;
@@ -554,6 +571,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   P.M = M;
   P.MU = MU;
   P.ff_identity = identity;
+  P.eval_layout = cfg.eval_layout;
   if (eval_lds_bytes(P) == 0)
     return fail(c, PAID_EINVAL, "frequency-sum table of %d rows does not fit in LDS (T too small against the band)",
                 P.tab_rows);
@@ -591,6 +609,18 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   P.counters = cnt + 4;     // [4..7]: done, not converged, work items
   P.gstats = reinterpret_cast<long long *>(cnt + 16);  // [16..23]
   P.out = out_dev ? out : c->outs.as<double>();
+  P.born = lockstep ? c->born.as<unsigned int>() : nullptr;
+  int *lcodes_dev = nullptr;
+  double *lq_dev = nullptr;
+  const size_t nlc = (size_t)n_ctr * (size_t)c->leaf_cap;
+  if (c->leaf_codes) {
+    int rl;
+    if ((rl = stage_out(c, c->leaf_codes, nlc * 3, c->lcodes, lcodes_dev)) != PAID_OK) return rl;
+    if ((rl = stage_out(c, c->leaf_q, nlc * MU, c->lq, lq_dev)) != PAID_OK) return rl;
+    P.leaf_codes = lcodes_dev;
+    P.leaf_q = lq_dev;
+    P.leaf_cap = c->leaf_cap;
+  }
   P.err_out = err_out ? (err_dev ? err_out : c->errs.as<double>()) : nullptr;
 
   HIPCHK(c, hipMemsetAsync(c->slot_i.p, 0, sizeof(int) * (8 * W + 8), c->stream));
@@ -741,6 +771,10 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   if (c->feat_out)
     HIPCHK(c, hipMemcpyAsync(c->feat_out, c->sfeat.p, sizeof(float) * kMlpIn * (size_t)n_ctr,
                              hipMemcpyDefault, c->stream));
+  if (c->leaf_codes) {
+    if ((rc = finish_out(c, c->leaf_codes, lcodes_dev, nlc * 3)) != PAID_OK) return rc;
+    if ((rc = finish_out(c, c->leaf_q, lq_dev, nlc * MU)) != PAID_OK) return rc;
+  }
   if (c->lab_out && P.labels != c->lab_out)
     HIPCHK(c, hipMemcpyAsync(c->lab_out, P.labels, sizeof(float) * kMlpOut * (size_t)n_ctr,
                              hipMemcpyDefault, c->stream));
@@ -893,6 +927,7 @@ int paid_children_eval(paid_ctx *c, const paid_params *p, const double *l, unsig
   P.M = M;
   P.MU = MU;
   P.ff_identity = identity;
+  P.eval_layout = cfg.eval_layout;
   if (eval_lds_bytes(P) == 0)
     return fail(c, PAID_EINVAL, "frequency-sum table of %d rows does not fit in LDS (T too small against the band)",
                 P.tab_rows);
@@ -962,6 +997,17 @@ int paid_set_seed_model(paid_ctx *c, const float *w, int dmax, double kappa) {
       return fail(c, PAID_EINVAL, "model weight %ld is not finite", i);
     }
   c->seed_on = true;
+  return PAID_OK;
+}
+
+int paid_set_leaf_output(paid_ctx *c, int *codes, double *q2n, long cap) {
+  if (!c) return PAID_EINVAL;
+  c->err.clear();
+  if ((codes == nullptr) != (q2n == nullptr) || (codes && cap < 1))
+    return fail(c, PAID_EINVAL, "codes and q2n both or neither, cap >= 1");
+  c->leaf_codes = codes;
+  c->leaf_q = q2n;
+  c->leaf_cap = codes ? cap : 0;
   return PAID_OK;
 }
 

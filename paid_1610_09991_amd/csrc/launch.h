@@ -10,10 +10,15 @@
 namespace paid {
 
 // rule constants, filled once per device (ascending node order on [-1,1])
+constexpr int kDelDepths = 29;  // parent depths 0..28
 struct RuleConst {
   double xi[kNF];   // fine nodes
   double w2[kNF];   // fine weights
   double w1[kNCo];  // coarse weights (at fine nodes 0,2,4,6,8)
+  // cos and sin of the offsets of a child's nodes from its centre,
+  // delta_a = (pi 2^-(d+1)) xi_a for parent depth d and a = 0..4 (the nodes
+  // a = 5..8 have the opposite offsets)
+  double cdel[kDelDepths][5], sdel[kDelDepths][5];
 };
 
 // ------------------------------------------------------------------ tables
@@ -59,6 +64,7 @@ struct Problem {      // everything the round kernels need, passed by value
   int lds_limit;              // bytes of LDS a workgroup may use on the device
   int eval_slots;             // evaluation workgroups resident at once (0: even partition)
   int sym;                    // 1: half zone p_y >= 0 with the parity factors of the pairs
+  int eval_layout;            // 0: the fastest evaluation kernel for the basis, 1: one wave per parent
   uint64_t *code;             // [W*cap]
   double *key;                // [W*cap]
   double *Q;                  // [W*cap*MU]
@@ -95,6 +101,13 @@ struct Problem {      // everything the round kernels need, passed by value
   float *labels;              // [n_ctr][256]
   // pair weights of the weighted global test (err_mode 2)
   const double *pair_w;       // [n_ctr][M][M] full-matrix weights
+  // one leaf per round (batch = batch_max = 1): creation index of every leaf,
+  // the exact worst leaf is selected, ties by creation order; NULL otherwise
+  unsigned int *born;         // [W*cap]
+  // leaves of finished containers, NULL = off
+  int *leaf_codes;            // [n_ctr][leaf_cap][3] (depth, ix, iy), -1 past the last leaf
+  double *leaf_q;             // [n_ctr][leaf_cap][MU]
+  long leaf_cap;
 };
 
 constexpr int kSeedG = 16;                    // cells per axis of the density grid

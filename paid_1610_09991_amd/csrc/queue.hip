@@ -272,6 +272,57 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     }
     return;
   }
+  if (P.born) {
+    // one leaf per round: the largest key, ties by creation order (the
+    // serial algorithm's heap order)
+    double bk = -1.0;
+    unsigned int bb = 0xFFFFFFFFu;
+    long bi = 0;
+    for (long i = t; i < n; i += blockDim.x) {
+      const double k = P.key[base + i];
+      const unsigned int b = P.born[base + i];
+      if (k > bk || (k == bk && b < bb)) {
+        bk = k;
+        bb = b;
+        bi = i;
+      }
+    }
+    for (int o = 32; o >= 1; o >>= 1) {  // within the wave
+      const double k2 = __shfl_xor(bk, o, 64);
+      const unsigned int b2 = __shfl_xor(bb, o, 64);
+      const long i2 = __shfl_xor(bi, o, 64);
+      if (k2 > bk || (k2 == bk && b2 < bb)) {
+        bk = k2;
+        bb = b2;
+        bi = i2;
+      }
+    }
+    if ((t & 63) == 0) {
+      shd[t >> 6] = bk;
+      shi[t >> 6] = (int)bb;
+      shi[kSelThreads / 64 + (t >> 6)] = (int)bi;
+    }
+    __syncthreads();
+    if (t == 0) {
+      for (int w2 = 1; w2 < (int)(blockDim.x >> 6); ++w2) {
+        const double k2 = shd[w2];
+        const unsigned int b2 = (unsigned int)shi[w2];
+        if (k2 > bk || (k2 == bk && b2 < bb)) {
+          bk = k2;
+          bb = b2;
+          bi = shi[kSelThreads / 64 + w2];
+        }
+      }
+      const int deep = code_depth(P.code[base + bi]) >= kMaxDepth;
+      P.sel[(long)s * P.bmax] = (int)bi;
+      P.selcnt[s] = deep ? 0 : 1;
+      if (deep) {
+        P.flags[s] |= 2;
+        P.state[s] = SLOT_DONE;
+      }
+    }
+    return;
+  }
   long kmaxl = (P.cap - n) / 3;
   if (kmaxl > P.bmax) kmaxl = P.bmax;
   if (kmaxl > n) kmaxl = n;
@@ -287,7 +338,10 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     hsum[b] = 0ull;
   }
   __syncthreads();
-  const double scale = maxkey > 0.0 ? 1099511627776.0 / maxkey : 0.0;  // 2^40 / maxkey
+  // fixed-point scale 2^(62 - ceil(log2 n)) / maxkey: n keys of at most maxkey
+  // sum to at most 2^62, so no bin, prefix or deficit overflows 64 bits
+  const int lgn = n > 1 ? 64 - __clzll((unsigned long long)(n - 1)) : 0;
+  const double scale = maxkey > 0.0 ? ldexp(1.0, 62 - lgn) / maxkey : 0.0;
   for (long i = t; i < n; i += blockDim.x) {
     double k = P.key[base + i];
     int b = key_bin(k, eb);
@@ -516,6 +570,22 @@ __global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
   if (P.flags[s] & 2) resum_errors(P, s, shd);  // budget exit: error sums from the leaves
   const long c = P.cid[s];
   if (P.labels) tree_labels(P, s, c, shd);
+  if (P.leaf_codes) {  // the leaves in pool order (codes and Q_2N), -1 past the last
+    const long n = P.nleaf[s], base = (long)s * P.cap;
+    for (long i = t; i < P.leaf_cap; i += blockDim.x) {
+      int *cd = P.leaf_codes + (c * P.leaf_cap + i) * 3;
+      if (i < n) {
+        const uint64_t code = P.code[base + i];
+        cd[0] = code_depth(code);
+        cd[1] = (int)code_ix(code);
+        cd[2] = (int)code_iy(code);
+        for (int k = 0; k < P.MU; ++k)
+          P.leaf_q[(c * P.leaf_cap + i) * P.MU + k] = P.Q[(base + i) * P.MU + k];
+      } else {
+        cd[0] = cd[1] = cd[2] = -1;
+      }
+    }
+  }
   const int M = P.M;
   for (int pid = t; pid < P.MU; pid += blockDim.x) {
     int p = 0, k = pid;

@@ -755,6 +755,8 @@ __global__ void __launch_bounds__(64) k_root(Problem P) {
     P.st_splits[s] = 0;
     P.st_evals[s] = placeholder ? 0 : nroot * kNF * kNF;
     P.st_depth[s] = nroot - 1;
+    if (P.born)
+      for (int h = 0; h < nroot; ++h) P.born[(long)s * P.cap + h] = h;
     P.flags[s] = P.seed_y ? kFlagSeed : 0;
     if (P.seed_y) P.seed_d[s] = D;
     P.state[s] = SLOT_ACTIVE;
@@ -819,6 +821,8 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
     int cx = ch & 1, cy = ch >> 1;
     long ri = (ch == 0) ? leaf : nold + 3L * r + (ch - 1);
     const uint64_t cc = make_code(d + 1, 2 * ix + cx, 2 * iy + cy);
+    if (P.born && lane == 0)  // the split is the container's st_splits-th (one per round)
+      P.born[(long)s * P.cap + ri] = (unsigned int)(1 + 4 * P.st_splits[s] + ch);
     if ((skip >> ch) & 1) {
       store_zero<L>(P, s, ri, cc);
       wave_sync();
@@ -906,6 +910,28 @@ __device__ inline const Problem &kernarg_problem(const Problem &P) {
 #endif
 }
 
+// Work items [i0, i1) of this workgroup.  Guided partition: workgroup b
+// starts at item total (1 - k^b) with k = 1 - 1/S, S the workgroups resident
+// at once, so the ranges shrink geometrically and the workgroups dispatched
+// last (the tail of the launch) are short; k is lowered where the grid would
+// otherwise leave its last workgroup more than four items.
+__device__ inline void item_range(const Problem &P, int &i0, int &i1) {
+  const int total = P.counters[2];
+  if (P.eval_slots > 0) {
+    const double keep = fmin(1.0 - 1.0 / (double)P.eval_slots,
+                             exp(log(4.0 / fmax((double)total, 4.0)) / (double)gridDim.x));
+    auto start = [&](int b) -> int {
+      return b >= (int)gridDim.x ? total : (int)((double)total * (1.0 - pow(keep, (double)b)));
+    };
+    i0 = start(blockIdx.x);
+    i1 = min(start(blockIdx.x + 1), total);
+  } else {
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    i0 = blockIdx.x * per;
+    i1 = min(i0 + per, total);
+  }
+}
+
 // Each workgroup takes a contiguous range of work items; its waves take every
 // nw-th item of it, so at any time they work on neighbouring parents, mostly
 // of one container and parameter row.  The range is cut into segments of
@@ -924,26 +950,8 @@ __global__ void __launch_bounds__(256) k_children(Problem P) {
   const int nw = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   WaveLds<L> &S = *reinterpret_cast<WaveLds<L> *>(lds_raw + (size_t)P.tab_rows * kTabStride +
                                                   (size_t)wv * P.lds_wave_doubles);
-  const int total = P.counters[2];
   int i0, i1;
-  if (P.eval_slots > 0) {
-    // guided partition: workgroup b starts at item total (1 - k^b) with
-    // k = 1 - 1/S, S the workgroups resident at once, so the ranges shrink
-    // geometrically and the workgroups dispatched last (the tail of the
-    // launch) are short; k is lowered where the grid would otherwise leave
-    // its last workgroup more than four items
-    const double keep = fmin(1.0 - 1.0 / (double)P.eval_slots,
-                             exp(log(4.0 / fmax((double)total, 4.0)) / (double)gridDim.x));
-    auto start = [&](int b) -> int {
-      return b >= (int)gridDim.x ? total : (int)((double)total * (1.0 - pow(keep, (double)b)));
-    };
-    i0 = start(blockIdx.x);
-    i1 = min(start(blockIdx.x + 1), total);
-  } else {
-    const int per = (total + gridDim.x - 1) / gridDim.x;
-    i0 = blockIdx.x * per;
-    i1 = min(i0 + per, total);
-  }
+  item_range(P, i0, i1);
   if (i0 >= i1) return;  // uniform in the workgroup
   build_pidmap<L>(pidmap, podd, threadIdx.x, blockDim.x);
   int s = item_slot(P, i0), lo = P.woff[s], hi = P.woff[s + 1];  // current slot, its items
@@ -983,6 +991,434 @@ __global__ void __launch_bounds__(256) k_children(Problem P) {
     if (seg < i1) {
       s = t;
       lo = P.woff[s];
+      hi = P.woff[s + 1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- two lanes per child
+// Region evaluation for the 9-function box basis (L = 1) with the separable
+// FP64 projection, arranged so that every sum stays in registers: a wave
+// holds 8 work items (parents); lane 8 it + 2 ch + h evaluates child ch of
+// item it together with its partner lane (h = 0, 1).  The products of two
+// box harmonics u_a u_c (u_0 = 1, u_1 = sqrt2 cos, u_2 = sqrt2 sin) lie in
+// the span of five functions phi = {1, sqrt2 cos, sqrt2 sin, cos 2x,
+// sin 2x} (2 cos^2 = 1 + cos 2x, 2 cos sin = sin 2x, 2 sin^2 = 1 - cos 2x),
+// so every pair of box functions of a rectangle is a signed sum of the 25
+// integrals I_jk = int g phi_j(x) phi_k(y).  Lane h = 0 accumulates I for
+// the fine rule (Q_2N); lane h = 1 accumulates the same sums with the weight
+// difference of the two rules (E = Q_2N - Q_N, the error estimate), so the
+// key of the child (sum over pairs of |E|) needs no lanes but its own.
+// The two lanes of a child share its 81 nodes column by column: lane 0
+// takes columns 0-3 and rows 0-4 of column 4, lane 1 columns 8-5 and rows
+// 5-8 of column 4; after each column the partners swap their y-sums so
+// that each adds both columns to its x-sums.  Nodes on the edges shared by
+// neighbouring children are evaluated once per child (324 evaluations for
+// the 289 distinct nodes of a parent).
+namespace lpc {
+
+constexpr int kItems = 8;              // work items per wave
+constexpr int kYRow = 6;               // doubles per node row: C, D, phi_1..phi_4
+// the 9 node rows of one child row, padded to an odd number of doubles so
+// that the blocks the lanes of a wave read at one time fall on distinct banks
+constexpr int kYBlock = kNF * kYRow + 1;
+constexpr int kYDoubles = kItems * 2 * kYBlock;  // per-wave LDS: rows of both child rows
+constexpr int kPairs = 45;             // pairs of the 9 box functions
+// per-wave LDS: the node rows, then per item the parent's Q, E and key weights
+__host__ __device__ constexpr int wave_doubles(bool with_e, bool with_w) {
+  return kYDoubles + kItems * kPairs * (1 + (with_e ? 1 : 0) + (with_w ? 1 : 0));
+}
+
+// phi index and sign of the terms of the product u_a u_c (a <= c)
+struct Terms {
+  int n, j0, s0, j1, s1;
+};
+__host__ __device__ constexpr Terms prod_terms(int a, int c) {
+  return (a == 0 && c == 0) ? Terms{1, 0, 1, 0, 0}
+       : (a == 0 && c == 1) ? Terms{1, 1, 1, 0, 0}
+       : (a == 0 && c == 2) ? Terms{1, 2, 1, 0, 0}
+       : (a == 1 && c == 1) ? Terms{2, 0, 1, 3, 1}
+       : (a == 1 && c == 2) ? Terms{1, 4, 1, 0, 0}
+                            : Terms{2, 0, 1, 3, -1};  // (2, 2)
+}
+
+// the 45 box pairs (m, n), m <= n, m = 3 a + b: x terms of u_am u_an
+// (phi index j0, optional j1 with sign) and y terms of u_bm u_bn; -1 = none
+struct PairTab {
+  signed char t[45][6];  // jx0, jx1, sx1, ky0, ky1, sy1
+};
+__host__ __device__ constexpr PairTab make_pair_tab() {
+  PairTab T{};
+  int p = 0;
+  for (int m = 0; m < 9; ++m)
+    for (int n = m; n < 9; ++n) {
+      const int am = m / 3, bm = m % 3, an = n / 3, bn = n % 3;
+      const Terms tx = prod_terms(am < an ? am : an, am < an ? an : am);
+      const Terms ty = prod_terms(bm < bn ? bm : bn, bm < bn ? bn : bm);
+      T.t[p][0] = (signed char)tx.j0;
+      T.t[p][1] = (signed char)(tx.n == 2 ? tx.j1 : -1);
+      T.t[p][2] = (signed char)tx.s1;
+      T.t[p][3] = (signed char)ty.j0;
+      T.t[p][4] = (signed char)(ty.n == 2 ? ty.j1 : -1);
+      T.t[p][5] = (signed char)ty.s1;
+      ++p;
+    }
+  return T;
+}
+
+// sum of v over the four children of the item, the same in all lanes of the
+// item with the same h: ((c0 + c1) + (c2 + c3)) with a + b = b + a exactly
+__device__ inline double child_sum(double v) {
+  v += dpp_move<0x4E>(v);                 // quad_perm [2,3,0,1]: child ch ^ 1, same h
+  const double o = dpp_move<0x141>(dpp_move<0xB1>(v));  // lane ^ 1, then 7 - lane: other quad, same h
+  return v + o;
+}
+
+__device__ inline double swap_h(double v) { return dpp_move<0xB1>(v); }  // partner lane (h ^ 1)
+
+}  // namespace lpc
+
+// Sine and cosine of one coordinate, out of line: the constants of the
+// series then live only while it runs instead of occupying registers across
+// the caller's loops.
+__device__ __noinline__ double2 sincos_out_of_line(double x) {
+  double sn, cs;
+  sincos_zone(x, &sn, &cs);
+  return make_double2(sn, cs);
+}
+
+// Slot, item and parent of lane group `it` of a wave whose first item is g0
+// in slot s0 (items g0 + it >= gend repeat the last item and store nothing).
+struct LpcItem {
+  int s, r;
+  long leaf, pbase;
+  uint64_t pc;
+};
+__device__ inline LpcItem lpc_item(const Problem &P, int w, int s0) {
+  LpcItem q;
+  int s = s0;
+  while (P.woff[s + 1] <= w) ++s;
+  q.s = s;
+  q.r = w - P.woff[s];
+  q.leaf = P.sel[(long)s * P.bmax + q.r];
+  q.pbase = (long)s * P.cap + q.leaf;
+  q.pc = P.code[q.pbase];
+  return q;
+}
+
+// One group of up to 8 work items of one parameter row (row entry E, table
+// tab in LDS), first item g0 in slot s0; items g0 + it >= gend are inactive
+// (their lanes repeat the last item and store nothing).
+// a value that is the same in every lane, held in scalar registers
+__device__ inline double wave_uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ void lpc_group(const Problem &P, int erow, const double *tab, double *Yw, int g0,
+                          int gend, int s0) {
+  using namespace lpc;
+  // the parameter row's constants in scalar registers (read for each group
+  // rather than held in vector registers across the kernel's loops)
+  const Entry &Erow = P.entries[erow];
+  Entry E;
+  E.t = wave_uniform(Erow.t);
+  E.tp = wave_uniform(Erow.tp);
+  E.mu = wave_uniform(Erow.mu);
+  E.w = wave_uniform(Erow.w);
+  E.inv_w = wave_uniform(Erow.inv_w);
+  E.J = __builtin_amdgcn_readfirstlane(Erow.J);
+  // the lane's place, formed anew for every group rather than held in
+  // registers across the kernel's loops
+  int lane = lane_id();
+  asm volatile("" : "+v"(lane));
+  const int it = lane >> 3, ch = (lane >> 1) & 3, h = lane & 1;
+  const int cx = ch & 1, cy = ch >> 1;
+  const int w = min(g0 + it, gend - 1);
+  const int MU = P.MU;
+  double *PQ = Yw + lpc::kYDoubles, *PE = PQ + kItems * lpc::kPairs;
+  double *PW = PE + (P.E ? kItems * lpc::kPairs : 0);
+
+  // ---- the items: parents' values, placeholders, node rows
+  int d, chl;
+  double cxm = 0.0, sxm = 0.0, cLx, sLx;
+  unsigned long long pm;
+  bool wave_skip;
+  {
+    const LpcItem q = lpc_item(P, w, s0);
+    const Ctr C = P.ctr[P.cid[q.s]];
+    chl = C.ch;
+    cLx = C.cLx;
+    sLx = C.sLx;
+    d = code_depth(q.pc);
+    const uint64_t ix = code_ix(q.pc), iy = code_iy(q.pc);
+    const uint64_t ccode = make_code(d + 1, 2 * ix + cx, 2 * iy + cy);
+    // seed phase: children the seed tree splits again are placeholders
+    const bool valid = g0 + it < gend;
+    const bool phc = P.seed_y && (P.flags[q.s] & kFlagSeed) && seed_split(P, q.s, ccode);
+    pm = __ballot(phc && valid);
+    wave_skip = pm == __ballot(valid);  // every child of the group is one
+    // the parents' values (their records are overwritten by child 0 below):
+    // Q, and E and the key weights where the mode uses them
+    for (int k = lane & 7; k < MU; k += 8) {
+      PQ[it * lpc::kPairs + k] = P.Q[q.pbase * MU + k];
+      if (P.E) PE[it * lpc::kPairs + k] = (double)P.E[q.pbase * MU + k];
+      if (P.err_mode != 0) PW[it * lpc::kPairs + k] = (double)P.itau[(long)q.s * MU + k];
+    }
+    // trigonometric values of the nodes by angle addition: node a of a child
+    // lies at offset delta_a (a table per depth) from the child's centre,
+    // whose sine and cosine each lane pair forms once (lane 0 for x, lane 1
+    // for y)
+    if (!wave_skip) {
+      const double wdt = kTwoPi * ldexp(1.0, -d);
+      const double xm = -kPi + (double)ix * wdt + (0.25 + 0.5 * cx) * wdt;
+      const double ym = -kPi + (double)iy * wdt + (0.25 + 0.5 * cy) * wdt;
+      const double2 sc = sincos_out_of_line(h ? ym : xm);
+      const double c1 = sc.y, s1 = sc.x;
+      const double c2 = lpc::swap_h(c1), s2 = lpc::swap_h(s1);
+      cxm = h ? c2 : c1;
+      sxm = h ? s2 : s1;
+      // rows of both child rows of every item: cos(l_y/2 + y), cos(l_y/2 - y), phi_1..4(y)
+#pragma unroll 1
+      for (int t0 = 0; t0 < kItems * 2 * kNF; t0 += 64) {
+        // every lane takes part in the exchanges; lanes past the last row idle after them
+        const int t = t0 + lane, ti = min(t / (2 * kNF), kItems - 1);
+        const int rem = t - ti * (2 * kNF), tcy = min(rem / kNF, 1), b = rem - tcy * kNF;
+        const int src = 8 * ti + 4 * tcy + 1;  // lane 1 of child (0, tcy) of item ti
+        const double cm = __shfl(c1, src, 64), sm = __shfl(s1, src, 64);
+        const double cL = __shfl(C.cLy, src, 64), sL = __shfl(C.sLy, src, 64);
+        const int td = __shfl(d, 8 * ti, 64);
+        if (t >= kItems * 2 * kNF) continue;
+        const int bb = b < 5 ? b : 8 - b;
+        const double cd = c_rule.cdel[td][bb];
+        const double sd = b < 5 ? c_rule.sdel[td][bb] : -c_rule.sdel[td][bb];
+        const double cyv = cm * cd - sm * sd, sy = sm * cd + cm * sd;
+        double *row = Yw + (ti * 2 + tcy) * kYBlock + b * kYRow;
+        row[0] = cL * cyv - sL * sy;  // cos(l_y/2 + y)
+        row[1] = cL * cyv + sL * sy;  // cos(l_y/2 - y)
+        row[2] = kSqrt2 * cyv;
+        row[3] = kSqrt2 * sy;
+        row[4] = (cyv - sy) * (cyv + sy);
+        row[5] = 2.0 * sy * cyv;
+      }
+    }
+  }
+  wave_sync();
+
+  // ---- the integrand and the sums
+  const double *Yc = Yw + (it * 2 + cy) * kYBlock;
+  const double mt2 = -2.0 * E.t, mtp4 = -4.0 * E.tp;
+  double I[5][5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) I[j][k] = 0.0;
+
+  // cos and sin of column a of this lane's child
+  auto column_trig = [&](int a, double &cxv, double &sx) {
+    const int aa = a < 5 ? a : 8 - a;
+    const double cd = c_rule.cdel[d][aa], sd = a < 5 ? c_rule.sdel[d][aa] : -c_rule.sdel[d][aa];
+    cxv = cxm * cd - sxm * sd;
+    sx = sxm * cd + cxm * sd;
+  };
+  // the integrand along rows [b0, b1) of column a: y-sums with the fine (H2)
+  // and the coarse (H1) weights
+  auto column = [&](int a, int b0, int b1, double (&H2)[5], double (&H1)[5]) {
+    double cxv, sx;
+    column_trig(a, cxv, sx);
+    const double Cx = cLx * cxv - sLx * sx, Dx = cLx * cxv + sLx * sx;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      H2[k] = 0.0;
+      H1[k] = 0.0;
+    }
+#pragma unroll 1
+    for (int b = b0; b < b1; ++b) {
+      const double *row = Yc + b * kYRow;
+      double g = 1.0;  // PAID_UNIT
+      if (P.kind <= 1) {
+        const double py = row[0], my = row[1];
+        const double ea = mt2 * (Cx + py) + mtp4 * Cx * py - E.mu;
+        const double eb = mt2 * (Dx + my) + mtp4 * Dx * my - E.mu;
+        g = K_eval(E, tab, chl, ea, eb);
+      }
+      const double g2 = c_rule.w2[b] * g, g1 = ((b & 1) ? 0.0 : c_rule.w1[b >> 1]) * g;
+      H2[0] += g2;
+      H1[0] += g1;
+#pragma unroll
+      for (int k = 1; k < 5; ++k) {
+        H2[k] = fma(g2, row[1 + k], H2[k]);
+        H1[k] = fma(g1, row[1 + k], H1[k]);
+      }
+    }
+  };
+  // phi_j at column a
+  auto column_basis = [&](int a, double (&px)[5]) {
+    double cxv, sx;
+    column_trig(a, cxv, sx);
+    px[0] = 1.0;
+    px[1] = kSqrt2 * cxv;
+    px[2] = kSqrt2 * sx;
+    px[3] = (cxv - sx) * (cxv + sx);
+    px[4] = 2.0 * sx * cxv;
+  };
+  // x-sums of one column from its y-sum vector dk: lane 0 adds the fine
+  // rule's sums (wf H2), lane 1 fine minus coarse (wf H2 - wc H1)
+  auto xsum = [&](const double (&dk)[5], const double (&px)[5]) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) I[0][k] += dk[k];
+#pragma unroll
+    for (int j = 1; j < 5; ++j)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) I[j][k] = fma(px[j], dk[k], I[j][k]);
+  };
+  // one step: this lane's column a and the partner's; each lane forms the
+  // y-sum vector the partner needs from its own column and swaps it
+  auto step = [&](int a, int b0, int b1, double wf, double wc, bool split) {
+    double H2[5], H1[5];
+    column(a, b0, b1, H2, H1);
+    if (split) {  // both lanes hold part of the same column: add the parts
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        H2[k] += lpc::swap_h(H2[k]);
+        H1[k] += lpc::swap_h(H1[k]);
+      }
+    }
+    const double wown = h ? wc : 0.0, wsend = h ? 0.0 : wc;
+    double dk[5], sk[5], px[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      dk[k] = fma(wf, H2[k], -wown * H1[k]);
+      sk[k] = fma(wf, H2[k], -wsend * H1[k]);
+    }
+    column_basis(a, px);
+    xsum(dk, px);
+    if (!split) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) sk[k] = lpc::swap_h(sk[k]);
+#pragma unroll
+      for (int j = 1; j < 5; ++j) px[j] = lpc::swap_h(px[j]);
+      xsum(sk, px);
+    }
+  };
+
+  if (!wave_skip) {
+    // columns s (lane 0) and 8 - s (lane 1), s = 0..3: the CC weights are
+    // symmetric, so both columns of a step carry the same weights
+#pragma unroll 1
+    for (int st = 0; st < 4; ++st)
+      step(h ? 8 - st : st, 0, kNF, c_rule.w2[st], (st & 1) ? 0.0 : c_rule.w1[st >> 1], false);
+    // column 4: rows 0-4 on lane 0, rows 5-8 on lane 1
+    step(4, h ? 5 : 0, h ? kNF : 5, c_rule.w2[4], c_rule.w1[2], true);
+  }
+  // the item's bookkeeping is read again below rather than held in
+  // registers across the loops above
+  asm volatile("" ::: "memory");
+
+  // ---- records: lane 0 writes the child's Q_2N, lane 1 its |E| and key;
+  // the lanes of child 0 write the item's deltas (children minus parent, the
+  // parent's values from LDS), summed over the four children
+  const LpcItem q = lpc_item(P, w, s0);
+  const bool valid = g0 + it < gend;
+  const int dd = code_depth(q.pc);
+  const uint64_t ix = code_ix(q.pc), iy = code_iy(q.pc);
+  const uint64_t ccode = make_code(dd + 1, 2 * ix + cx, 2 * iy + cy);
+  const bool phc = (pm >> lane) & 1ull;
+  const bool item_skip = ((pm >> (8 * it)) & 0xFFull) == 0xFFull;
+  const double pkey = P.key[q.pbase];
+  const double wdt = kTwoPi * ldexp(1.0, -dd);
+  const double fa = (0.25 * wdt) * (0.25 * wdt) / (4.0 * kPi * kPi);
+  const long ri = (ch == 0) ? q.leaf : (long)P.nleaf[q.s] + 3L * q.r + (ch - 1);
+  const long base = (long)q.s * P.cap + ri;
+  const long itm = (long)q.s * P.bmax + q.r;
+  const bool head = valid && ch == 0;
+  const double *par = (h ? PE : PQ) + it * lpc::kPairs;
+  const double *wgt = P.err_mode != 0 ? PW + it * lpc::kPairs : nullptr;
+  double *dst = h ? P.dep : P.dv;
+  double key = 0.0;
+  constexpr lpc::PairTab PT = lpc::make_pair_tab();
+#pragma unroll
+  for (int p = 0; p < lpc::kPairs; ++p) {
+    const signed char *tp = PT.t[p];
+    double v = I[tp[0]][tp[3]];
+    if (tp[4] >= 0) v = tp[5] > 0 ? v + I[tp[0]][tp[4]] : v - I[tp[0]][tp[4]];
+    if (tp[1] >= 0) {
+      double u = I[tp[1]][tp[3]];
+      if (tp[4] >= 0) u = tp[5] > 0 ? u + I[tp[1]][tp[4]] : u - I[tp[1]][tp[4]];
+      v = tp[2] > 0 ? v + u : v - u;
+    }
+    const double x = phc ? 0.0 : fa * v;  // lane 0: Q_2N of the pair, lane 1: E
+    const double e = fabs(x);
+    const float ef = (float)e;
+    key += wgt ? e * wgt[p] : e;
+    if (h == 0) {
+      if (valid) P.Q[base * MU + p] = x;
+    } else if (valid && P.E) {
+      P.E[base * MU + p] = ef;
+    }
+    // the same float-rounded error that is stored and later subtracted
+    const double sum = lpc::child_sum(h ? (double)ef : x);
+    if (head && dst) dst[itm * MU + p] = sum - par[p];
+  }
+  // child keys (lane 1) and the item's key delta
+  const double kk = lpc::child_sum(h ? key : 0.0);
+  if (valid) {
+    if (h == 1) P.key[base] = key;
+    else P.code[base] = ccode;
+    if (P.born && h == 0) P.born[base] = (unsigned int)(1 + 4 * P.st_splits[q.s] + ch);
+  }
+  if (head && h == 1) P.de[itm] = kk - pkey;
+  if (head && h == 0) {
+    if (P.ifill) P.ifill[itm] = !item_skip;
+    if (dd + 1 > P.st_depth[q.s]) atomicMax(&P.st_depth[q.s], dd + 1);
+  }
+}
+
+// The same work partition and table staging as k_children; inside a segment
+// (items of one parameter row) wave wv takes the groups of 8 items that
+// start at seg + 8 (wv + nw k).
+__global__ void __launch_bounds__(256) k_children_lpc(Problem P) {
+  extern __shared__ double lds_raw[];
+  double *tabl = lds_raw;
+  const int nw = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *Yw = lds_raw + (size_t)P.tab_rows * kTabStride + (size_t)wv * P.lds_wave_doubles;
+  int i0, i1;
+  item_range(P, i0, i1);
+  if (i0 >= i1) return;  // uniform in the workgroup
+  int s = item_slot(P, i0), hi = P.woff[s + 1];
+  int seg = i0, loaded = -1;
+#pragma unroll 1
+  while (seg < i1) {
+    const int e = __builtin_amdgcn_readfirstlane(slot_entry(P, s));
+    int t = s + 1;
+    while (t < P.W && P.woff[t] < i1 && (P.woff[t + 1] == P.woff[t] || slot_entry(P, t) == e)) ++t;
+    const int seg_hi = (t < P.W && P.woff[t] < i1) ? P.woff[t] : i1;
+    if (e != loaded) {
+      __syncthreads();  // every wave is done with the previous table
+      const Entry E0 = P.entries[e];
+      const double *src = P.tab + E0.tab_off;
+      for (int i = threadIdx.x; i < E0.J * kTabStride; i += blockDim.x) tabl[i] = src[i];
+      __syncthreads();
+      loaded = e;
+    }
+#pragma unroll 1
+    for (int g = seg + lpc::kItems * wv; g < seg_hi; g += lpc::kItems * nw) {
+      if (g >= hi) {  // slot holding item g (woff is non-decreasing)
+        int a = s + 1, b = P.W;  // woff[a] <= g < woff[b]
+        while (b - a > 1) {
+          const int mid = (a + b) >> 1;
+          if (P.woff[mid] <= g) a = mid; else b = mid;
+        }
+        s = a;
+        hi = P.woff[s + 1];
+      }
+      lpc_group(kernarg_problem(P), e, tabl, Yw, g, seg_hi, s);
+    }
+    seg = seg_hi;
+    if (seg < i1) {
+      s = t;
       hi = P.woff[s + 1];
     }
   }
@@ -1044,12 +1480,39 @@ hipError_t launch_eval_t(Problem p, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// per-wave LDS of the two-lanes-per-child kernel (doubles)
+int lpc_wave_doubles(const Problem &p) {
+  return lpc::wave_doubles(p.E != nullptr, p.err_mode != 0);
+}
+
+// Dynamic LDS of the two-lanes-per-child kernel: the table and each wave's
+// node rows and parent values, up to 4 waves in 64 KiB (or in the device
+// limit for long tables)
+size_t lpc_lds(const Problem &p, int *waves_out) {
+  const size_t wave_b = sizeof(double) * lpc_wave_doubles(p);
+  const size_t tab_b = sizeof(double) * (size_t)p.tab_rows * kTabStride;
+  size_t budget = 65536;
+  if (tab_b + wave_b > budget) budget = p.lds_limit > 0 ? (size_t)p.lds_limit : 65536;
+  if (tab_b + wave_b > budget) return 0;
+  int waves = (int)((budget - tab_b) / wave_b);
+  waves = waves > 4 ? 4 : waves;
+  if (waves_out) *waves_out = waves;
+  return tab_b + (size_t)waves * wave_b;
+}
+
 }  // namespace
 
 namespace {
 // projection/precision mode of a problem: separable FP64, or the dense Gram
 // in the requested precision
 int gram_mode(const Problem &p) { return p.gram == PAID_GRAM_SEPARABLE ? kSep : p.precision; }
+
+// the two-lanes-per-child kernel serves the 9-function box basis itself with
+// the separable FP64 projection over the full zone (bubble and unit integrands)
+bool use_lpc(const Problem &p) {
+  return p.eval_layout == 0 && p.L == 1 && p.ff_identity && !p.sym && gram_mode(p) == kSep &&
+         p.kind != PAID_GAUSS;
+}
 
 template <int L>
 hipError_t launch_root_l(const Problem &p, hipStream_t s) {
@@ -1091,6 +1554,7 @@ hipError_t launch_root(const Problem &p, hipStream_t s) {
 }
 
 size_t eval_lds_bytes(const Problem &p) {
+  if (use_lpc(p)) return lpc_lds(p, nullptr);
   switch (p.L) {
     case 0: return eval_lds_t<0>(p, nullptr, nullptr);
     case 1: return eval_lds_t<1>(p, nullptr, nullptr);
@@ -1099,6 +1563,15 @@ size_t eval_lds_bytes(const Problem &p) {
 }
 
 int eval_occupancy(const Problem &p) {
+  if (use_lpc(p)) {
+    int waves = 0, n = 0;
+    const size_t sh = lpc_lds(p, &waves);
+    if (sh == 0) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_children_lpc),
+                                                     64 * waves, sh) != hipSuccess || n < 1)
+      n = 1;
+    return n;
+  }
   switch (p.L) {
     case 0: return eval_occupancy_l<0>(p);
     case 1: return eval_occupancy_l<1>(p);
@@ -1107,6 +1580,15 @@ int eval_occupancy(const Problem &p) {
 }
 
 hipError_t launch_eval(const Problem &p, int grid, hipStream_t s) {
+  if (use_lpc(p)) {
+    int waves = 0;
+    const size_t sh = lpc_lds(p, &waves);
+    if (sh == 0) return hipErrorInvalidValue;
+    Problem q = p;
+    q.lds_wave_doubles = lpc_wave_doubles(p);
+    hipLaunchKernelGGL(k_children_lpc, dim3(grid), dim3(64 * waves), sh, s, q);
+    return hipGetLastError();
+  }
   switch (p.L) {
     case 0: return launch_eval_l<0>(p, grid, s);
     case 1: return launch_eval_l<1>(p, grid, s);
