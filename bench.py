@@ -63,8 +63,8 @@ K_FLOPS_PER_NODE = 80
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2516
-TRAFFIC_SOURCES_SHA256 = "3e32f81387270ca2219c07a17feffcf5e6e88672484002a1ee0508db45cc74de"
+TRAFFIC_BYTES_PER_ITEM = 2499
+TRAFFIC_SOURCES_SHA256 = "9ec82ab4bfcaa1c7a7183ddeee5a25f2e95de1edc9f708e5ca176bf5388fd7a9"
 NODES_PER_ITEM = 289
 
 # per-workload launch settings of the secondary measurements: the region

@@ -26,23 +26,26 @@ constexpr int kMaxMU = kMaxMB * (kMaxMB + 1) / 2;
 // K_pp(a,b) = -S[a,-b].  S is analytic except at x = +-i w_n, so on short
 // intervals of x >= 0 it is a short Taylor series.  In units of w = pi T
 // (the distance of the nearest singularity from the real axis) the
-// intervals are: 9 central ones centred at 0, 1/8, ..., 1 with half-width
-// 1/16, then 8 per octave, [2^e (1 + m/8), 2^e (1 + (m+1)/8)), m = 0..7, so
-// the index follows from the exponent and top mantissa bits of |x|/w.  Every
-// half-width is at most 1/16 of the distance from its centre to the nearest
-// singularity, which makes degree 13 exact to rounding on the interval (and
-// accurate out to 1.5 half-widths, where the divided difference of two close
-// energies is formed on the polynomial of one of them).
-// Row layout: -c/h, 1/h, coef[14] of P(t) = S(c + h t), one double of
-// padding.  c/h is an integer (2j in the centre, 17 + 2m in an octave), so
-// t = x/h - c/h is one fused multiply-add.  An odd stride in doubles (136
-// bytes) spreads the rows that the lanes of a wave read at one coefficient
-// over the LDS banks (18 and 20 doubles are slower, 16 much slower).
+// intervals are: P + 1 central ones centred at 0, 1/P, ..., 1 with
+// half-width 1/(2P), then P per octave, [2^e (1 + m/P), 2^e (1 + (m+1)/P)),
+// m = 0..P-1, so the index follows from the exponent and top log2(P)
+// mantissa bits of |x|/w.  Every half-width is at most 1/(2P) of the
+// distance from its centre to the nearest singularity; with P = 8, degree 13
+// is exact to rounding on the interval (and accurate out to 1.5 half-widths,
+// where the divided difference of two close energies is formed on the
+// polynomial of one of them).
+// Row layout: -c/h, 1/h, coef[deg + 1] of P(t) = S(c + h t), padded to an odd
+// number of doubles.  c/h is an integer (2j in the centre, 2P + 1 + 2m in an
+// octave), so t = x/h - c/h is one fused multiply-add.  An odd stride in
+// doubles spreads the rows that the lanes of a wave read at one coefficient
+// over the LDS banks (with P = 8, 18 and 20 doubles are slower than 17, 16
+// much slower).
 constexpr int kTabDeg = 13;
-constexpr int kTabStride = 17;                 // -c/h, 1/h, coef[14], 1 pad (odd: spreads rows over LDS banks)
+constexpr int kTabLogOct = 3;                  // log2 of the intervals per octave
+constexpr int kTabPerOct = 1 << kTabLogOct;    // intervals per octave above |x| = w
+constexpr int kTabCentral = kTabPerOct + 1;    // central intervals
+constexpr int kTabStride = (kTabDeg + 3) | 1;  // -c/h, 1/h, coef[deg + 1], odd
 constexpr int kTabCoef = 2;                    // offset of the coefficients in a row
-constexpr int kTabCentral = 9;                 // central intervals
-constexpr int kTabPerOct = 8;                  // intervals per octave above |x| = w
 constexpr int kTabPts = 32;                    // Cauchy points per interval
 constexpr double kTabRho = 2.0;                // Cauchy radius in half-widths
 constexpr int kTabKTail = 24;                  // tail expansion terms
@@ -50,14 +53,15 @@ constexpr double kDdSwitch2 = 0.0004;          // (0.02)^2: close-pair switch
 
 // interval j in units of w: centre c and half-width h (j >= 0)
 __host__ __device__ inline void tab_interval(int j, double w, double &c, double &h) {
+  constexpr double inv_p = 1.0 / kTabPerOct;
   if (j < kTabCentral) {
-    c = w * (0.125 * j);
-    h = w * 0.0625;
+    c = w * (inv_p * j);
+    h = w * (0.5 * inv_p);
   } else {
     const int k = j - kTabCentral, e = k / kTabPerOct, m = k - e * kTabPerOct;
     const double s = ldexp(w, e);
-    c = s * (1.0 + 0.125 * (m + 0.5));
-    h = s * 0.0625;
+    c = s * (1.0 + inv_p * (m + 0.5));
+    h = s * (0.5 * inv_p);
   }
 }
 
@@ -97,11 +101,11 @@ __host__ __device__ inline uint64_t code_iy(uint64_t c) { return c & 0xFFFFFFFul
 // Frequency-sum table evaluation.
 // interval of |x| (no transcendental: exponent and top mantissa bits of |x|/w).
 // Both candidates are formed and one is selected, without a branch; for
-// v >= 1 the bits above the top three mantissa bits are (exponent << 3 | m).
+// v >= 1 the bits above the top log2(P) mantissa bits are (exponent << log2(P) | m).
 __device__ inline int tab_index(const Entry &e, double ax) {
   const float v = (float)(ax * e.inv_w);
-  const int jc = (int)fmaf(fminf(v, 1.0f), 8.0f, 0.5f);
-  const int jo = kTabCentral - 127 * kTabPerOct + (int)(__float_as_uint(v) >> 20);
+  const int jc = (int)fmaf(fminf(v, 1.0f), (float)kTabPerOct, 0.5f);
+  const int jo = kTabCentral - 127 * kTabPerOct + (int)(__float_as_uint(v) >> (23 - kTabLogOct));
   const int j = v < 1.0f ? jc : jo;
   return j < e.J - 1 ? j : e.J - 1;
 }

@@ -1024,9 +1024,11 @@ constexpr int kYRow = 6;               // doubles per node row: C, D, phi_1..phi
 constexpr int kYBlock = kNF * kYRow + 1;
 constexpr int kYDoubles = kItems * 2 * kYBlock;  // per-wave LDS: rows of both child rows
 constexpr int kPairs = 45;             // pairs of the 9 box functions
-// per-wave LDS: the node rows, then per item the parent's Q, E and key weights
+// per-wave LDS: the node rows while the sums run, then (in the same space)
+// per item the parent's Q, E and key weights for the records
 __host__ __device__ constexpr int wave_doubles(bool with_e, bool with_w) {
-  return kYDoubles + kItems * kPairs * (1 + (with_e ? 1 : 0) + (with_w ? 1 : 0));
+  const int par = kItems * kPairs * (1 + (with_e ? 1 : 0) + (with_w ? 1 : 0));
+  return par > kYDoubles ? par : kYDoubles;
 }
 
 // phi index and sign of the terms of the product u_a u_c (a <= c)
@@ -1138,10 +1140,8 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
   const int cx = ch & 1, cy = ch >> 1;
   const int w = min(g0 + it, gend - 1);
   const int MU = P.MU;
-  double *PQ = Yw + lpc::kYDoubles, *PE = PQ + kItems * lpc::kPairs;
-  double *PW = PE + (P.E ? kItems * lpc::kPairs : 0);
 
-  // ---- the items: parents' values, placeholders, node rows
+  // ---- the items: placeholders, node rows
   int d, chl;
   double cxm = 0.0, sxm = 0.0, cLx, sLx;
   unsigned long long pm;
@@ -1160,13 +1160,6 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
     const bool phc = P.seed_y && (P.flags[q.s] & kFlagSeed) && seed_split(P, q.s, ccode);
     pm = __ballot(phc && valid);
     wave_skip = pm == __ballot(valid);  // every child of the group is one
-    // the parents' values (their records are overwritten by child 0 below):
-    // Q, and E and the key weights where the mode uses them
-    for (int k = lane & 7; k < MU; k += 8) {
-      PQ[it * lpc::kPairs + k] = P.Q[q.pbase * MU + k];
-      if (P.E) PE[it * lpc::kPairs + k] = (double)P.E[q.pbase * MU + k];
-      if (P.err_mode != 0) PW[it * lpc::kPairs + k] = (double)P.itau[(long)q.s * MU + k];
-    }
     // trigonometric values of the nodes by angle addition: node a of a child
     // lies at offset delta_a (a table per depth) from the child's centre,
     // whose sine and cosine each lane pair forms once (lane 0 for x, lane 1
@@ -1321,6 +1314,17 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
   // the lanes of child 0 write the item's deltas (children minus parent, the
   // parent's values from LDS), summed over the four children
   const LpcItem q = lpc_item(P, w, s0);
+  // the parents' values (their records are overwritten by child 0 below):
+  // Q, and E and the key weights where the mode uses them, in the LDS that
+  // held the node rows
+  double *PQ = Yw, *PE = PQ + kItems * lpc::kPairs;
+  double *PW = PE + (P.E ? kItems * lpc::kPairs : 0);
+  for (int k = lane & 7; k < MU; k += 8) {
+    PQ[it * lpc::kPairs + k] = P.Q[q.pbase * MU + k];
+    if (P.E) PE[it * lpc::kPairs + k] = (double)P.E[q.pbase * MU + k];
+    if (P.err_mode != 0) PW[it * lpc::kPairs + k] = (double)P.itau[(long)q.s * MU + k];
+  }
+  wave_sync();
   const bool valid = g0 + it < gend;
   const int dd = code_depth(q.pc);
   const uint64_t ix = code_ix(q.pc), iy = code_iy(q.pc);
@@ -1379,7 +1383,7 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
 // The same work partition and table staging as k_children; inside a segment
 // (items of one parameter row) wave wv takes the groups of 8 items that
 // start at seg + 8 (wv + nw k).
-__global__ void __launch_bounds__(256) k_children_lpc(Problem P) {
+__global__ void __launch_bounds__(512) k_children_lpc(Problem P) {
   extern __shared__ double lds_raw[];
   double *tabl = lds_raw;
   const int nw = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1486,18 +1490,40 @@ int lpc_wave_doubles(const Problem &p) {
 }
 
 // Dynamic LDS of the two-lanes-per-child kernel: the table and each wave's
-// node rows and parent values, up to 4 waves in 64 KiB (or in the device
-// limit for long tables)
+// node rows and parent values.  The table is staged once per workgroup, so
+// the number of waves per workgroup (4, 6 or 8; fewer only if nothing else
+// fits the device's per-workgroup limit) is the one that keeps the most
+// waves resident per CU, by the runtime's occupancy calculator; the choice
+// is remembered per table and wave size.
 size_t lpc_lds(const Problem &p, int *waves_out) {
   const size_t wave_b = sizeof(double) * lpc_wave_doubles(p);
   const size_t tab_b = sizeof(double) * (size_t)p.tab_rows * kTabStride;
-  size_t budget = 65536;
-  if (tab_b + wave_b > budget) budget = p.lds_limit > 0 ? (size_t)p.lds_limit : 65536;
-  if (tab_b + wave_b > budget) return 0;
-  int waves = (int)((budget - tab_b) / wave_b);
-  waves = waves > 4 ? 4 : waves;
-  if (waves_out) *waves_out = waves;
-  return tab_b + (size_t)waves * wave_b;
+  const size_t limit = p.lds_limit > 0 ? (size_t)p.lds_limit : 65536;
+  thread_local size_t memo_tab = 0, memo_wave = 0, memo_limit = 0;
+  thread_local int memo_waves = 0;
+  if (memo_waves == 0 || memo_tab != tab_b || memo_wave != wave_b || memo_limit != limit) {
+    int best = 0, best_w = 0;
+    for (int w : {4, 6, 8, 2, 1}) {
+      const size_t sh = tab_b + (size_t)w * wave_b;
+      if (sh > limit || (best > 0 && w < 4)) continue;
+      int n = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &n, reinterpret_cast<const void *>(&k_children_lpc), 64 * w, sh) != hipSuccess)
+        n = 0;
+      if (n < 1) n = (w < 4 && best == 0) ? 1 : 0;  // a last resort still runs
+      if (n * w > best) {
+        best = n * w;
+        best_w = w;
+      }
+    }
+    if (best_w == 0) return 0;
+    memo_tab = tab_b;
+    memo_wave = wave_b;
+    memo_limit = limit;
+    memo_waves = best_w;
+  }
+  if (waves_out) *waves_out = memo_waves;
+  return tab_b + (size_t)memo_waves * wave_b;
 }
 
 }  // namespace

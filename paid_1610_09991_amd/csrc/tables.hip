@@ -117,8 +117,9 @@ __global__ void k_tab_coef(TabArgs a) {
   double c, h;
   tab_interval(j, E.w, c, h);
   if (k == 0) {
-    // -c/h, exact: 2j for a central interval, 17 + 2m for interval m of an octave
-    row[0] = -(double)(j < kTabCentral ? 2 * j : 17 + 2 * ((j - kTabCentral) % kTabPerOct));
+    // -c/h, exact: 2j for a central interval, 2P + 1 + 2m for interval m of an octave
+    row[0] = -(double)(j < kTabCentral ? 2 * j
+                                       : 2 * kTabPerOct + 1 + 2 * ((j - kTabCentral) % kTabPerOct));
     row[1] = 1.0 / h;
   }
   double coef = 0.0;
