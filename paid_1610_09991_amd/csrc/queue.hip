@@ -327,10 +327,20 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
   if (kmaxl > P.bmax) kmaxl = P.bmax;
   if (kmaxl > n) kmaxl = n;
   const int kmax = (int)kmaxl;
-  // pass 1: largest key
-  double mk = 0.0;
-  for (long i = t; i < n; i += blockDim.x) mk = fmax(mk, P.key[base + i]);
-  const double maxkey = block_max(mk, shd);
+  // pass 1: largest key (four loads in flight per thread)
+  const long st = blockDim.x;
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+  {
+    long i = t;
+    for (; i + 3 * st < n; i += 4 * st) {
+      m0 = fmax(m0, P.key[base + i]);
+      m1 = fmax(m1, P.key[base + i + st]);
+      m2 = fmax(m2, P.key[base + i + 2 * st]);
+      m3 = fmax(m3, P.key[base + i + 3 * st]);
+    }
+    for (; i < n; i += st) m0 = fmax(m0, P.key[base + i]);
+  }
+  const double maxkey = block_max(fmax(fmax(m0, m1), fmax(m2, m3)), shd);
   const int eb = (int)(__double_as_longlong(maxkey > 0.0 ? maxkey : 1.0) >> 50);
   // pass 2: histogram of counts and fixed-point sums (exact, order-free)
   for (int b = t; b < kBins; b += blockDim.x) {
@@ -342,11 +352,25 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
   // sum to at most 2^62, so no bin, prefix or deficit overflows 64 bits
   const int lgn = n > 1 ? 64 - __clzll((unsigned long long)(n - 1)) : 0;
   const double scale = maxkey > 0.0 ? ldexp(1.0, 62 - lgn) / maxkey : 0.0;
-  for (long i = t; i < n; i += blockDim.x) {
-    double k = P.key[base + i];
-    int b = key_bin(k, eb);
-    atomicAdd(&hcnt[b], 1u);
-    atomicAdd(&hsum[b], (unsigned long long)(k * scale));
+  {
+    long i = t;
+    for (; i + 3 * st < n; i += 4 * st) {
+      double k[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) k[j] = P.key[base + i + j * st];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int b = key_bin(k[j], eb);
+        atomicAdd(&hcnt[b], 1u);
+        atomicAdd(&hsum[b], (unsigned long long)(k[j] * scale));
+      }
+    }
+    for (; i < n; i += st) {
+      const double k = P.key[base + i];
+      const int b = key_bin(k, eb);
+      atomicAdd(&hcnt[b], 1u);
+      atomicAdd(&hsum[b], (unsigned long long)(k * scale));
+    }
   }
   __syncthreads();
   if (t < 64) {  // one wave scans the bins: 8 per lane
@@ -428,25 +452,36 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
   }
   __syncthreads();
   const int bfull = s_bfull, bpart = s_bpart, part = s_part;
-  // pass 3: order-preserving compaction
+  // pass 3: order-preserving compaction, four consecutive leaves per thread
+  // and chunk.  One scan of both counts (16 bits each): the leaves of bin
+  // bpart are taken in index order while room is left, so the place of a
+  // taken leaf follows from the full-bin leaves and the bpart leaves before it
   int out = 0, seenpart = 0;
   int *sel = P.sel + (long)s * P.bmax;
-  for (long b0 = 0; b0 < n; b0 += blockDim.x) {
-    long i = b0 + t;
-    int bin = (i < n) ? key_bin(P.key[base + i], eb) : kBins;
-    // one scan of both flags (16 bits each): the leaves of bin bpart are
-    // taken in index order while room is left, so the prefix of the taken
-    // ones follows from that of bin bpart's
-    const int isp = (i < n && bin == bpart) ? 1 : 0, full = (i < n && bin <= bfull) ? 1 : 0;
+  for (long b0 = 0; b0 < n; b0 += 4 * st) {
+    const long i0 = b0 + 4 * t;
+    int isp[4], full[4], np = 0, nf = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int bin = (i0 + j < n) ? key_bin(P.key[base + i0 + j], eb) : kBins;
+      isp[j] = (bin == bpart && i0 + j < n) ? 1 : 0;
+      full[j] = (bin <= bfull && i0 + j < n) ? 1 : 0;
+      np += isp[j];
+      nf += full[j];
+    }
     int ex;
-    const int tot = block_scan(isp | (full << 16), shi, ex);
-    const int ex1 = ex & 0xFFFF, totp = tot & 0xFFFF;
+    const int tot = block_scan(np | (nf << 16), shi, ex);
+    const int totp = tot & 0xFFFF;
     const int room = part - seenpart > 0 ? part - seenpart : 0;
-    const int flag = full || (isp && ex1 < room);
-    const int ex2 = (ex >> 16) + (ex1 < room ? ex1 : room);
-    const int totf = (tot >> 16) + (totp < room ? totp : room);
-    if (flag && out + ex2 < s_k) sel[out + ex2] = (int)i;
-    out += totf;
+    int rp = ex & 0xFFFF, rf = ex >> 16;  // bpart and full-bin leaves before this one
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int pos = out + rf + (rp < room ? rp : room);
+      if ((full[j] || (isp[j] && rp < room)) && pos < s_k) sel[pos] = (int)(i0 + j);
+      rp += isp[j];
+      rf += full[j];
+    }
+    out += (tot >> 16) + (totp < room ? totp : room);
     seenpart += totp;
     if (out >= s_k) break;
   }
