@@ -64,7 +64,7 @@ K_FLOPS_PER_NODE = 80
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
 TRAFFIC_BYTES_PER_ITEM = 2501
-TRAFFIC_SOURCES_SHA256 = "9ec82ab4bfcaa1c7a7183ddeee5a25f2e95de1edc9f708e5ca176bf5388fd7a9"
+TRAFFIC_SOURCES_SHA256 = "38af270d29caaf4cdc295e7c7d6f221b61eb4a7c4ae4a1a2aa80bb041c041d9e"
 NODES_PER_ITEM = 289
 
 # Per-workload region budget (max_regions): the smallest power of two that

@@ -56,7 +56,7 @@ struct paid_ctx {
   DevBuf code, key, Q, E;
   DevBuf slot_i, slot_d, sel, dv, de, dep, itau, errp, stl, counters, outs, errs;
   // learned seeding
-  DevBuf seedw, sfeat, sfold, sy, sact, pyr, seedd, ifill, labtmp;
+  DevBuf seedw, sfeat, sfold, sy, sact, pyr, seedd, ifill, labtmp, rowsz, rperm;
   bool seed_on = false;
   int seed_dmax = 8;
   double seed_kappa = 2.0;
@@ -451,7 +451,7 @@ void paid_destroy(paid_ctx *c) {
                     &c->errp,    &c->stl,  &c->counters, &c->outs, &c->errs,
                     &c->seedw,   &c->sfeat, &c->sfold, &c->sy,  &c->sact,  &c->pyr,
                     &c->seedd,   &c->ifill, &c->labtmp, &c->pairw, &c->born, &c->lcodes,
-                    &c->lq};
+                    &c->lq,      &c->rowsz, &c->rperm};
   for (DevBuf *b : bufs) b->release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -675,7 +675,26 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
       P.seed_dmax = c->seed_dmax;
       P.seed_thresh = 4.0 * c->seed_kappa;
       P.seed_limit = cap / 4;
+      // admission order: the parameter rows by predicted leaves, largest
+      // first (ties by row), so that the deepest trees start early and the
+      // call does not end on a few of them; each row's containers stay
+      // together (one table per run of slots in the evaluation kernel)
+      const int per_row = n_q * n_ch;
+      HIPCHK(c, c->rowsz.ensure(sizeof(double) * (size_t)n_params));
+      HIPCHK(c, c->rperm.ensure(sizeof(int) * (size_t)n_params));
+      HIPCHK(c, launch_seed_rowsize(c->sy.as<float>(), n_params, per_row, c->rowsz.as<double>(), c->stream));
+      std::vector<double> rsz(n_params);
+      HIPCHK(c, hipMemcpyAsync(rsz.data(), c->rowsz.p, sizeof(double) * n_params, hipMemcpyDeviceToHost,
+                               c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
+      std::vector<int> perm(n_params);
+      for (int r = 0; r < n_params; ++r) perm[r] = r;
+      std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return rsz[a] > rsz[b]; });
+      HIPCHK(c, hipMemcpyAsync(c->rperm.p, perm.data(), sizeof(int) * n_params, hipMemcpyHostToDevice,
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      P.row_perm = c->rperm.as<int>();
+      P.per_row = per_row;
     }
     if (c->lab_out) {
       if (is_device_ptr(c->lab_out)) {

@@ -95,6 +95,10 @@ struct Problem {      // everything the round kernels need, passed by value
   int seed_dmax;
   double seed_thresh;         // split while the predicted count >= this
   long seed_limit;            // most leaves a seed tree may have
+  // admission order (NULL: container index order): queue position k takes
+  // container row_perm[k / per_row] * per_row + k % per_row
+  const int *row_perm;        // [n_params] parameter rows, largest predicted trees first
+  int per_row;                // containers per parameter row (q points x channels)
   long *st_evals;             // [W] integrand evaluations
   int *ifill;                 // [W*bmax] 1 if the work item evaluated its node grid
   // tree labels of finished containers (model frame), NULL = off
@@ -148,6 +152,9 @@ __device__ inline bool seed_split(const Problem &P, int s, uint64_t code) {
 }
 
 hipError_t launch_admit(const Problem &p, hipStream_t s);
+// predicted leaves of every parameter row (sum over its containers and cells
+// of max(0, 2^y - 1)), in a fixed summation order
+hipError_t launch_seed_rowsize(const float *y, int n_rows, int per_row, double *out, hipStream_t s);
 hipError_t launch_root(const Problem &p, hipStream_t s);
 hipError_t launch_select(const Problem &p, hipStream_t s);
 hipError_t launch_worklist(const Problem &p, hipStream_t s);

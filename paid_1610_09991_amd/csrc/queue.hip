@@ -532,7 +532,8 @@ __global__ void k_worklist(Problem P) {
   }
 }
 
-// Container admission: empty slots take the next containers in slot order.
+// Container admission: empty slots take the next containers of the queue in
+// slot order.
 __global__ void k_admit(Problem P) {
   __shared__ int shi[1024];
   __shared__ int s_head;
@@ -545,7 +546,8 @@ __global__ void k_admit(Problem P) {
     int s = b0 + t, e = (s < P.W && P.state[s] == SLOT_EMPTY) ? 1 : 0, ex;
     int tot = block_scan(e, shi, ex);
     if (e && head + ex < P.n_ctr) {
-      P.cid[s] = head + ex;
+      const int k = head + ex;
+      P.cid[s] = P.row_perm ? P.row_perm[k / P.per_row] * P.per_row + k % P.per_row : k;
       P.state[s] = SLOT_NEW;
     }
     head += tot;
@@ -661,6 +663,26 @@ __global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
 }
 
 }  // namespace
+
+// Predicted leaves of parameter row r: the sum over its containers (a
+// contiguous block of per_row) and the 256 model cells of max(0, 2^y - 1).
+__global__ void __launch_bounds__(kSelThreads) k_seed_rowsize(const float *y, int per_row, double *out) {
+  __shared__ double shd[2 * kSelThreads];
+  const long n = (long)per_row * kMlpOut, base = (long)blockIdx.x * n;
+  double a = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = exp2((double)y[base + i]) - 1.0;
+    a += v > 0.0 ? v : 0.0;
+  }
+  const double tot = block_sum(a, shd);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+hipError_t launch_seed_rowsize(const float *y, int n_rows, int per_row, double *out, hipStream_t s) {
+  if (n_rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seed_rowsize, dim3(n_rows), dim3(kSelThreads), 0, s, y, per_row, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_admit(const Problem &p, hipStream_t s) {
   hipLaunchKernelGGL(k_admit, dim3(1), dim3(1024), 0, s, p);

@@ -1108,9 +1108,6 @@ __device__ inline LpcItem lpc_item(const Problem &P, int w, int s0) {
   return q;
 }
 
-// One group of up to 8 work items of one parameter row (row entry E, table
-// tab in LDS), first item g0 in slot s0; items g0 + it >= gend are inactive
-// (their lanes repeat the last item and store nothing).
 // a value that is the same in every lane, held in scalar registers
 __device__ inline double wave_uniform(double v) {
   const long long b = __double_as_longlong(v);
@@ -1119,6 +1116,10 @@ __device__ inline double wave_uniform(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// One group of up to 8 work items of one parameter row (row entry erow,
+// table tab in LDS, the wave's LDS at Yw), first item g0 in slot s0; items
+// g0 + it >= gend are inactive (their lanes repeat the last item and store
+// nothing).
 __device__ void lpc_group(const Problem &P, int erow, const double *tab, double *Yw, int g0,
                           int gend, int s0) {
   using namespace lpc;
