@@ -63,8 +63,8 @@ K_FLOPS_PER_NODE = 80
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2501
-TRAFFIC_SOURCES_SHA256 = "38af270d29caaf4cdc295e7c7d6f221b61eb4a7c4ae4a1a2aa80bb041c041d9e"
+TRAFFIC_BYTES_PER_ITEM = 2505
+TRAFFIC_SOURCES_SHA256 = "629a06c382e7eb9ad37834c05d18529cedecdc8d6c6c904dd25db1cecc5106c6"
 NODES_PER_ITEM = 289
 
 # Per-workload region budget (max_regions): the smallest power of two that
@@ -75,6 +75,12 @@ NODES_PER_ITEM = 289
 # per call; C5 likewise -9%).  A container that reaches its budget stops
 # with PAID_ENOCONV, which makes the benchmark fail.
 BUDGET = {"C2": 1 << 17, "C3": 1 << 19, "C5": 1 << 17, "C2_per_integral": 1 << 19}
+# Two kinds of pool slots (paid_config.small_regions / big_share) where they
+# pay: C3's containers start in slots of 2^17 leaves and the few that outgrow
+# them move to slots of 2^19 (a quarter of the pool): 2,785 resident
+# containers instead of 858 and the same trees (-11% per call).  On C2 and in
+# the per-integral mode more resident containers were slower.
+POOL = {"C3": {"small_regions": 1 << 17, "big_share": 0.25}}
 
 
 def kernel_sources_sha256() -> str:
@@ -149,12 +155,14 @@ def cpu_baseline(cfg, budget_s: float, threads: int, seed: int = 11, nq: int = 4
 class Runner:
     """One library context and output buffer for one workload."""
 
-    def __init__(self, P, torch, cfg, stream, tuned, err_mode, max_regions, args):
+    def __init__(self, P, torch, cfg, stream, tuned, err_mode, max_regions, args, pool=None):
         self.P, self.torch, self.cfg = P, torch, cfg
         prec = {"fp64": P.FP64, "fp32": P.FP32, "bf16x3": P.BF16X3}[args.precision]
         kw = dict(tuned)
         if max_regions:
             kw["max_regions"] = max_regions
+        if pool:
+            kw.update(pool)
         self.ctx = P.Context(stream=stream.cuda_stream, profile=1, precision=prec,
                              graph=args.graph, eval_layout=args.eval_layout,
                              gram=P.GRAM_SEPARABLE if args.gram == "separable" else P.GRAM_MFMA,
@@ -331,7 +339,8 @@ def main():
     cfg = W.config(args.workload)
     budget = BUDGET.get(args.workload if args.err_mode == "global"
                         else args.workload + "_per_integral", 1 << 20)
-    run = Runner(P, torch, cfg, stream, tuned, em_head, budget, args)
+    run = Runner(P, torch, cfg, stream, tuned, em_head, budget, args,
+                 POOL.get(args.workload) if args.err_mode == "global" else None)
     variants = {}
     res, st_b, dt_b = run.timed("batched", args.warmup if model is None else min(args.warmup, 1),
                                 args.steps if model is None else min(args.steps, 3))
@@ -357,7 +366,8 @@ def main():
                                    "batched_learned": "batched, learned seeding"}[head],
                        "err_mode": args.err_mode, "rule": "Clenshaw-Curtis N=4/2N=8",
                        "launch": {"graph": args.graph, "eval_layout": args.eval_layout,
-                                  "max_regions": budget, **tuned},
+                                  "max_regions": budget, **tuned,
+                                  **(POOL.get(args.workload, {}) if args.err_mode == "global" else {})},
                        "regions_per_step": hv["regions"]},
             "roofline": roof, "variants": variants}
     if line_parity is not None:
@@ -410,9 +420,10 @@ def main():
         others = {}
         for wl in ("C3", "C5"):
             wcfg = W.config(wl)
-            wrun = Runner(P, torch, wcfg, stream, tuned, P.ERR_GLOBAL, BUDGET[wl], args)
+            wrun = Runner(P, torch, wcfg, stream, tuned, P.ERR_GLOBAL, BUDGET[wl], args, POOL.get(wl))
             entry = {"workload": f"{wcfg['name']}: {wcfg['desc']}", "containers": wrun.n_ctr,
-                     "integrals_per_step": wrun.n_int, "max_regions": BUDGET[wl], "variants": {}}
+                     "integrals_per_step": wrun.n_int, "max_regions": BUDGET[wl],
+                     "pool": POOL.get(wl, {}), "variants": {}}
             res, st, dtw = wrun.timed(f"{wl} batched", 1, sec_steps)
             entry["variants"]["batched"] = res
             if model is not None:

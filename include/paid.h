@@ -136,6 +136,20 @@ typedef struct {
                            sums in registers; otherwise one wave per parent),
                            1 always one wave per parent.  Both compute the same
                            rule sums, in different rounding orders */
+  long small_regions;   /* 0 (default): every resident container may hold
+                           max_regions leaves.  16 <= small_regions <
+                           max_regions: two kinds of slots share the pool.
+                           New containers start in small slots of
+                           small_regions leaves; a container whose next round
+                           could overflow its small slot moves (leaves and
+                           sums copied) to a large slot of max_regions leaves
+                           and waits until one is free.  The trees and results
+                           are those of one kind of slot of max_regions: a
+                           container never splits fewer leaves because of the
+                           small slot.  When few containers need the full
+                           budget, more are resident at once */
+  double big_share;     /* share of the pool for the large slots, in (0, 1);
+                           0: 0.25 */
 } paid_config;
 
 /* one parameter row: dispersion, temperature and flow scale */

@@ -39,7 +39,7 @@ class Config(C.Structure):
                 ("max_active", C.c_int), ("pool_gib", C.c_double),
                 ("gauss", C.c_double * 3), ("stream", C.c_void_p), ("profile", C.c_int),
                 ("graph", C.c_int), ("eval_wg_per_cu", C.c_int), ("symmetry", C.c_int),
-                ("eval_layout", C.c_int)]
+                ("eval_layout", C.c_int), ("small_regions", C.c_long), ("big_share", C.c_double)]
 
 
 class Params(C.Structure):

@@ -56,7 +56,7 @@ struct paid_ctx {
   DevBuf code, key, Q, E;
   DevBuf slot_i, slot_d, sel, dv, de, dep, itau, errp, stl, counters, outs, errs;
   // learned seeding
-  DevBuf seedw, sfeat, sfold, sy, sact, pyr, seedd, ifill, labtmp, rowsz, rperm;
+  DevBuf seedw, sfeat, sfold, sy, sact, pyr, seedd, ifill, labtmp, rowsz, rperm, movei;
   bool seed_on = false;
   int seed_dmax = 8;
   double seed_kappa = 2.0;
@@ -392,6 +392,9 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
     return fail(nullptr, PAID_EINVAL, "bad gram mode");
   if (cfg.kind < 0 || cfg.kind > 3) return fail(nullptr, PAID_EINVAL, "bad kind");
   if (cfg.kind == PAID_GAUSS && !(cfg.gauss[2] > 0)) return fail(nullptr, PAID_EINVAL, "gauss width must be > 0");
+  if (cfg.small_regions < 0 || (cfg.small_regions > 0 && cfg.small_regions < 16))
+    return fail(nullptr, PAID_EINVAL, "small_regions must be 0 or >= 16");
+  if (cfg.big_share < 0 || cfg.big_share >= 1) return fail(nullptr, PAID_EINVAL, "big_share must lie in [0, 1)");
   if (cfg.max_regions < 16 || cfg.max_regions > (1L << 28))
     return fail(nullptr, PAID_EINVAL, "max_regions must be in [16, 2^28]");
   if (!(cfg.nu >= 0)) return fail(nullptr, PAID_EINVAL, "nu must be >= 0");
@@ -451,7 +454,7 @@ void paid_destroy(paid_ctx *c) {
                     &c->errp,    &c->stl,  &c->counters, &c->outs, &c->errs,
                     &c->seedw,   &c->sfeat, &c->sfold, &c->sy,  &c->sact,  &c->pyr,
                     &c->seedd,   &c->ifill, &c->labtmp, &c->pairw, &c->born, &c->lcodes,
-                    &c->lq,      &c->rowsz, &c->rperm};
+                    &c->lq,      &c->rowsz, &c->rperm, &c->movei};
   for (DevBuf *b : bufs) b->release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -509,26 +512,46 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   HIPCHK(c, c->ctr.ensure(sizeof(Ctr) * n_ctr));
   HIPCHK(c, launch_container_setup(c->ctr.as<Ctr>(), n_ctr, c->qv.as<double>(), n_q, n_ch, ch_first, c->stream));
 
-  // pool: slots x capacity
-  const long cap = cfg.max_regions;
+  // pool: slots x capacity; with small_regions, large slots (capb) first,
+  // then small ones (cap)
+  const long capb = cfg.max_regions;
+  const bool two = cfg.small_regions > 0 && cfg.small_regions < capb;
+  const long cap = two ? cfg.small_regions : capb;
   const size_t rec = 16 + 8 * (size_t)MU + (store_E ? 4 * (size_t)MU : 0);
-  size_t pool_bytes;
+  size_t pool_bytes, rest_bytes = 0;  // rest: for the per-slot round buffers (0: unchecked)
   if (cfg.pool_gib > 0) {
     pool_bytes = (size_t)(cfg.pool_gib * 1073741824.0);
   } else {
     size_t fr = 0, tot = 0;
     HIPCHK(c, hipMemGetInfo(&fr, &tot));
-    pool_bytes = (size_t)(0.55 * (double)(fr + c->code.n + c->key.n + c->Q.n + c->E.n));
+    const double avail = (double)(fr + c->code.n + c->key.n + c->Q.n + c->E.n + c->dv.n + c->dep.n);
+    pool_bytes = (size_t)(0.55 * avail);
+    rest_bytes = (size_t)(0.35 * avail);
   }
-  long W = cfg.max_active > 0 ? cfg.max_active : (long)(pool_bytes / ((size_t)cap * rec));
-  if (W > n_ctr) W = n_ctr;
-  if (W > 65536) W = 65536;
-  if (W < 1) return fail(c, PAID_ENOMEM, "region pool too small for one container of %ld regions", cap);
+  long Wb = 0;
+  if (two) {
+    const double share = cfg.big_share > 0 ? cfg.big_share : 0.25;
+    Wb = (long)(share * (double)pool_bytes / ((double)capb * rec));
+    if (Wb < 1) Wb = 1;
+    if (Wb > n_ctr) Wb = n_ctr;
+  }
+  const size_t big_bytes = (size_t)Wb * capb * rec;
+  long Ws = cfg.max_active > 0 ? cfg.max_active - Wb
+                               : (pool_bytes > big_bytes ? (long)((pool_bytes - big_bytes) / ((size_t)cap * rec)) : 0);
+  if (Ws > n_ctr) Ws = n_ctr;
+  if (Wb + Ws > 65536) Ws = 65536 - Wb;
+  // the round buffers of every slot (deltas, selections) must fit beside the pool
+  const size_t slot_rest = (size_t)cfg.batch_max * (8 * (size_t)MU * (store_E ? 2 : 1) + 16) + 32 * (size_t)MU;
+  if (rest_bytes > 0 && (size_t)(Wb + Ws) * slot_rest > rest_bytes) Ws = (long)(rest_bytes / slot_rest) - Wb;
+  if (Ws < 1) return fail(c, PAID_ENOMEM, "region pool too small for one container of %ld regions", cap);
+  const long W = Wb + Ws;
+  const size_t regions = (size_t)Wb * capb + (size_t)Ws * cap;
   const int bmax = cfg.batch_max, bmin = cfg.batch;
-  HIPCHK(c, c->code.ensure(sizeof(uint64_t) * W * cap));
-  HIPCHK(c, c->key.ensure(sizeof(double) * W * cap));
-  HIPCHK(c, c->Q.ensure(sizeof(double) * W * cap * MU));
-  if (store_E) HIPCHK(c, c->E.ensure(sizeof(float) * W * cap * MU));
+  HIPCHK(c, c->code.ensure(sizeof(uint64_t) * regions));
+  HIPCHK(c, c->key.ensure(sizeof(double) * regions));
+  HIPCHK(c, c->Q.ensure(sizeof(double) * regions * MU));
+  if (store_E) HIPCHK(c, c->E.ensure(sizeof(float) * regions * MU));
+  HIPCHK(c, c->movei.ensure(sizeof(int) * (size_t)(W + Wb + 1)));
   HIPCHK(c, c->slot_i.ensure(sizeof(int) * (8 * W + 8)));
   HIPCHK(c, c->slot_d.ensure(sizeof(double) * (W * (size_t)MU + W)));
   HIPCHK(c, c->errp.ensure(sizeof(double) * W * (size_t)MU));
@@ -540,7 +563,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   HIPCHK(c, c->stl.ensure(sizeof(long) * 3 * W));
   HIPCHK(c, c->ifill.ensure(sizeof(int) * W * (size_t)bmax));
   const bool lockstep = bmin == 1 && bmax == 1;
-  if (lockstep) HIPCHK(c, c->born.ensure(sizeof(unsigned int) * W * (size_t)cap));
+  if (lockstep) HIPCHK(c, c->born.ensure(sizeof(unsigned int) * regions));
   HIPCHK(c, c->counters.ensure(256));
   const bool out_dev = is_device_ptr(out), err_dev = err_out && is_device_ptr(err_out);
   const size_t out_bytes = sizeof(double) * (size_t)n_ctr * M * M;
@@ -578,6 +601,10 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   P.ffc = c->ffc.as<double>();
   P.W = (int)W;
   P.cap = cap;
+  P.Wb = (int)Wb;
+  P.capb = capb;
+  P.moveq = c->movei.as<int>();
+  P.promo = P.moveq + W;
   P.bmin = bmin;
   P.bmax = bmax;
   P.code = c->code.as<uint64_t>();
@@ -674,7 +701,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
       P.seed_d = c->seedd.as<int>();
       P.seed_dmax = c->seed_dmax;
       P.seed_thresh = 4.0 * c->seed_kappa;
-      P.seed_limit = cap / 4;
+      P.seed_limit = cap / 4;  // a seed tree fits a small slot
       // admission order: the parameter rows by predicted leaves, largest
       // first (ties by row), so that the deepest trees start early and the
       // call does not end on a few of them; each row's containers stay
@@ -727,6 +754,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   auto part = [&](int k, hipStream_t st) -> hipError_t {
     hipError_t e;
     if (k == 0) {
+      if ((e = launch_move(P, st)) != hipSuccess) return e;
       if ((e = launch_admit(P, st)) != hipSuccess) return e;
       if ((e = launch_root(P, st)) != hipSuccess) return e;
       if ((e = launch_select(P, st)) != hipSuccess) return e;
@@ -781,7 +809,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
       eval_ms += ms;
     }
     if (c->host_counters[0] >= n_ctr) break;
-    if (rounds > 4L * cap + 64L * (n_ctr / W + 1))
+    if (rounds > 4L * capb + 64L * (n_ctr / Ws + 1))
       return fail(c, PAID_EINTERNAL, "round loop did not finish (%ld rounds)", rounds);
   }
   if (!out_dev) HIPCHK(c, hipMemcpyAsync(out, c->outs.p, out_bytes, hipMemcpyDeviceToHost, c->stream));

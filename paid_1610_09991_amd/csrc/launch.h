@@ -37,7 +37,8 @@ hipError_t launch_container_setup(Ctr *ctr, int n_ctr, const double *q, int n_q,
                                   int ch_first, hipStream_t s);
 
 // ------------------------------------------------------------------ pool and queue
-enum SlotState { SLOT_EMPTY = 0, SLOT_NEW = 1, SLOT_ACTIVE = 2, SLOT_DONE = 3 };
+// SLOT_MOVE: a container in a small slot waiting for a large one
+enum SlotState { SLOT_EMPTY = 0, SLOT_NEW = 1, SLOT_ACTIVE = 2, SLOT_DONE = 3, SLOT_MOVE = 4 };
 
 struct Problem {      // everything the round kernels need, passed by value
   // static description
@@ -57,7 +58,11 @@ struct Problem {      // everything the round kernels need, passed by value
   const double *ffc;          // [M][MB]
   // pool
   int W;                      // slots
-  long cap;                   // regions per slot
+  long cap;                   // regions per slot (per small slot when Wb > 0)
+  int Wb;                     // large slots 0..Wb-1 of capb regions each (0: one kind)
+  long capb;                  // regions per large slot
+  int *promo;                 // [Wb] small slot moving into each large slot this round, -1: none
+  int *moveq;                 // [W] scratch: the waiting small slots in slot order
   int bmin, bmax;
   int lds_wave_doubles;       // per-wave LDS of the evaluation kernel (set at launch)
   int tab_rows;               // rows of the largest frequency-sum table (the LDS table)
@@ -65,10 +70,10 @@ struct Problem {      // everything the round kernels need, passed by value
   int eval_slots;             // evaluation workgroups resident at once (0: even partition)
   int sym;                    // 1: half zone p_y >= 0 with the parity factors of the pairs
   int eval_layout;            // 0: the fastest evaluation kernel for the basis, 1: one wave per parent
-  uint64_t *code;             // [W*cap]
-  double *key;                // [W*cap]
-  double *Q;                  // [W*cap*MU]
-  float *E;                   // [W*cap*MU] or NULL
+  uint64_t *code;             // [regions], slot s from slot_base(s)
+  double *key;                // [regions]
+  double *Q;                  // [regions*MU]
+  float *E;                   // [regions*MU] or NULL
   // slot state
   int *cid, *state, *nleaf, *selcnt, *sel, *woff;  // sel: [W*bmax], woff: [W+1]
   int *flags;                 // [W]: bit0 = converged, bit1 = budget hit
@@ -107,12 +112,18 @@ struct Problem {      // everything the round kernels need, passed by value
   const double *pair_w;       // [n_ctr][M][M] full-matrix weights
   // one leaf per round (batch = batch_max = 1): creation index of every leaf,
   // the exact worst leaf is selected, ties by creation order; NULL otherwise
-  unsigned int *born;         // [W*cap]
+  unsigned int *born;         // [regions]
   // leaves of finished containers, NULL = off
   int *leaf_codes;            // [n_ctr][leaf_cap][3] (depth, ix, iy), -1 past the last leaf
   double *leaf_q;             // [n_ctr][leaf_cap][MU]
   long leaf_cap;
 };
+
+// first region and capacity of slot s (the large slots come first)
+__host__ __device__ inline long slot_base(const Problem &P, int s) {
+  return s < P.Wb ? (long)s * P.capb : (long)P.Wb * P.capb + (long)(s - P.Wb) * P.cap;
+}
+__host__ __device__ inline long slot_cap(const Problem &P, int s) { return s < P.Wb ? P.capb : P.cap; }
 
 constexpr int kSeedG = 16;                    // cells per axis of the density grid
 constexpr int kPyr = 1 + 4 + 16 + 64 + 256;   // pyramid levels 0..4
@@ -152,6 +163,8 @@ __device__ inline bool seed_split(const Problem &P, int s, uint64_t code) {
 }
 
 hipError_t launch_admit(const Problem &p, hipStream_t s);
+// moves of waiting containers from small to large slots (p.Wb > 0)
+hipError_t launch_move(const Problem &p, hipStream_t s);
 // predicted leaves of every parameter row (sum over its containers and cells
 // of max(0, 2^y - 1)), in a fixed summation order
 hipError_t launch_seed_rowsize(const float *y, int n_rows, int per_row, double *out, hipStream_t s);

@@ -141,7 +141,7 @@ __device__ void column_sums(const T *A, long rows, int ncol, double *out, double
 // of Q over the leaves (updated at every split).
 __device__ double resum_errors(const Problem &P, int s, double *shd) {
   const int t = threadIdx.x;
-  const long n = P.nleaf[s], base = (long)s * P.cap;
+  const long n = P.nleaf[s], base = slot_base(P, s);
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   long i = t;
   const long st = blockDim.x;
@@ -239,8 +239,8 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     // seed phase: the leaves the seed tree splits, in index order; no
     // termination test while placeholders may exist.  The seed tree has at
     // most cap/4 leaves, so the capacity is never reached here.
-    const long n = P.nleaf[s], base = (long)s * P.cap;
-    long kl = (P.cap - n) / 3;
+    const long n = P.nleaf[s], base = slot_base(P, s);
+    long kl = (slot_cap(P, s) - n) / 3;
     if (kl > P.bmax) kl = P.bmax;
     if (kl > n) kl = n;
     const int kmax = (int)kl;
@@ -275,12 +275,19 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     }
     return;
   }
-  const long n = P.nleaf[s], base = (long)s * P.cap;
-  if (n + 3 > P.cap) {
+  const long n = P.nleaf[s], base = slot_base(P, s), cap = slot_cap(P, s);
+  // in a small slot the container moves to a large one rather than split
+  // fewer leaves than it would there
+  const bool movable = P.Wb > 0 && s >= P.Wb;
+  if (n + 3 > cap) {
     if (t == 0) {
       P.selcnt[s] = 0;
-      P.flags[s] |= 2;
-      P.state[s] = SLOT_DONE;
+      if (movable) {
+        P.state[s] = SLOT_MOVE;
+      } else {
+        P.flags[s] |= 2;
+        P.state[s] = SLOT_DONE;
+      }
     }
     return;
   }
@@ -335,7 +342,7 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     }
     return;
   }
-  long kmaxl = (P.cap - n) / 3;
+  long kmaxl = ((movable ? P.capb : cap) - n) / 3;
   if (kmaxl > P.bmax) kmaxl = P.bmax;
   if (kmaxl > n) kmaxl = n;
   const int kmax = (int)kmaxl;
@@ -463,6 +470,13 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     }
   }
   __syncthreads();
+  if (movable && n + 3L * s_k > cap) {  // the round would overflow the small slot
+    if (t == 0) {
+      P.selcnt[s] = 0;
+      P.state[s] = SLOT_MOVE;
+    }
+    return;
+  }
   const int bfull = s_bfull, bpart = s_bpart, part = s_part;
   // pass 3: order-preserving compaction, four consecutive leaves per thread
   // and chunk.  One scan of both counts (16 bits each): the leaves of bin
@@ -543,7 +557,8 @@ __global__ void k_admit(Problem P) {
   if (s_head >= P.n_ctr) return;
   int head = s_head;
   for (int b0 = 0; b0 < P.W; b0 += blockDim.x) {
-    int s = b0 + t, e = (s < P.W && P.state[s] == SLOT_EMPTY) ? 1 : 0, ex;
+    // new containers start in small slots (all slots when there is one kind)
+    int s = b0 + t, e = (s < P.W && s >= P.Wb && P.state[s] == SLOT_EMPTY) ? 1 : 0, ex;
     int tot = block_scan(e, shi, ex);
     if (e && head + ex < P.n_ctr) {
       const int k = head + ex;
@@ -593,7 +608,7 @@ __device__ void tree_labels(const Problem &P, int s, long c, double *cnt) {
   const int t = threadIdx.x;
   for (int k = t; k < kSeedG * kSeedG; k += blockDim.x) cnt[k] = 0.0;
   __syncthreads();
-  const long n = P.nleaf[s], base = (long)s * P.cap;
+  const long n = P.nleaf[s], base = slot_base(P, s);
   for (long i = t; i < n; i += blockDim.x) {
     const uint64_t code = P.code[base + i];
     const int d = code_depth(code), ix = (int)code_ix(code), iy = (int)code_iy(code);
@@ -620,7 +635,7 @@ __global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
   const long c = P.cid[s];
   if (P.labels) tree_labels(P, s, c, shd);
   if (P.leaf_codes) {  // the leaves in pool order (codes and Q_2N), -1 past the last
-    const long n = P.nleaf[s], base = (long)s * P.cap;
+    const long n = P.nleaf[s], base = slot_base(P, s);
     for (long i = t; i < P.leaf_cap; i += blockDim.x) {
       int *cd = P.leaf_codes + (c * P.leaf_cap + i) * 3;
       if (i < n) {
@@ -663,6 +678,92 @@ __global__ void __launch_bounds__(kSelThreads) k_finalize(Problem P) {
 }
 
 }  // namespace
+
+// Moves from small to large slots, matched in slot order: the k-th waiting
+// small slot takes the k-th free large slot (promo[b]: the small slot moving
+// into large slot b this round, -1 if none).  One workgroup.
+__global__ void k_move_match(Problem P) {
+  __shared__ int shi[1024];
+  const int t = threadIdx.x;
+  int nw = 0;  // waiting small slots, in slot order, into moveq
+  for (int b0 = P.Wb; b0 < P.W; b0 += blockDim.x) {
+    const int s = b0 + t, e = (s < P.W && P.state[s] == SLOT_MOVE) ? 1 : 0;
+    int ex;
+    const int tot = block_scan(e, shi, ex);
+    if (e) P.moveq[nw + ex] = s;
+    nw += tot;
+  }
+  __syncthreads();  // moveq complete
+  int nf = 0;  // free large slots so far
+  for (int b0 = 0; b0 < P.Wb; b0 += blockDim.x) {
+    const int b = b0 + t, e = (b < P.Wb && P.state[b] == SLOT_EMPTY) ? 1 : 0;
+    int ex;
+    const int tot = block_scan(e, shi, ex);
+    if (b < P.Wb) P.promo[b] = (e && nf + ex < nw) ? P.moveq[nf + ex] : -1;
+    nf += tot;
+  }
+}
+
+// the leaves of each moving container, copied to its large slot (grid: large
+// slots x chunks of the leaf range)
+__global__ void k_move_copy(Problem P) {
+  const int b = blockIdx.x, src = P.promo[b];
+  if (src < 0) return;
+  const long n = P.nleaf[src], per = (n + gridDim.y - 1) / gridDim.y;
+  const long i0 = (long)blockIdx.y * per, i1 = i0 + per < n ? i0 + per : n;
+  if (i0 >= i1) return;
+  const long sb = slot_base(P, src), db = slot_base(P, b);
+  for (long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    P.code[db + i] = P.code[sb + i];
+    P.key[db + i] = P.key[sb + i];
+    if (P.born) P.born[db + i] = P.born[sb + i];
+  }
+  const long MU = P.MU;
+  for (long e = i0 * MU + threadIdx.x; e < i1 * MU; e += blockDim.x) {
+    P.Q[db * MU + e] = P.Q[sb * MU + e];
+    if (P.E) P.E[db * MU + e] = P.E[sb * MU + e];
+  }
+}
+
+// the moving containers' sums and bookkeeping; the large slot becomes active
+// and the small one free for the next admission (grid: large slots)
+__global__ void k_move_finish(Problem P) {
+  const int b = blockIdx.x, src = P.promo[b], t = threadIdx.x;
+  if (src < 0) return;
+  const long MU = P.MU;
+  for (long pid = t; pid < MU; pid += blockDim.x) {
+    P.val[(long)b * MU + pid] = P.val[(long)src * MU + pid];
+    P.itau[(long)b * MU + pid] = P.itau[(long)src * MU + pid];
+    if (P.errp) P.errp[(long)b * MU + pid] = P.errp[(long)src * MU + pid];
+  }
+  if (P.pyr)
+    for (int k = t; k < kPyr; k += blockDim.x) P.pyr[(long)b * kPyr + k] = P.pyr[(long)src * kPyr + k];
+  if (t == 0) {
+    P.cid[b] = P.cid[src];
+    P.nleaf[b] = P.nleaf[src];
+    P.flags[b] = P.flags[src];
+    P.st_depth[b] = P.st_depth[src];
+    P.st_rounds[b] = P.st_rounds[src];
+    P.st_splits[b] = P.st_splits[src];
+    P.st_evals[b] = P.st_evals[src];
+    P.err[b] = P.err[src];
+    if (P.seed_d) P.seed_d[b] = P.seed_d[src];
+    P.selcnt[b] = 0;
+    P.selcnt[src] = 0;
+    P.state[b] = SLOT_ACTIVE;
+    P.state[src] = SLOT_EMPTY;
+  }
+}
+
+constexpr int kMoveChunks = 64;  // workgroups per moving container in k_move_copy
+
+hipError_t launch_move(const Problem &p, hipStream_t s) {
+  if (p.Wb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_move_match, dim3(1), dim3(1024), 0, s, p);
+  hipLaunchKernelGGL(k_move_copy, dim3(p.Wb, kMoveChunks), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_move_finish, dim3(p.Wb), dim3(64), 0, s, p);
+  return hipGetLastError();
+}
 
 // Predicted leaves of parameter row r: the sum over its containers (a
 // contiguous block of per_row) and the 256 model cells of max(0, 2^y - 1).

@@ -563,7 +563,7 @@ __device__ inline double wave_sum(double v) {
 template <int L>
 __device__ double store_region(WaveLds<L> &S, const Problem &P, int s, long ri, uint64_t code) {
   const int lane = lane_id();
-  const long base = (long)s * P.cap + ri;
+  const long base = slot_base(P, s) + ri;
   double part = 0.0;
   for (int pid = lane; pid < P.MU; pid += 64) {
     double q = S.cq[pid], e = fabs(S.ce[pid]);
@@ -617,7 +617,7 @@ __device__ void build_pidmap(int *map, int *odd, int tid, int nthr) {
 template <int L>
 __device__ void store_zero(const Problem &P, int s, long ri, uint64_t code) {
   const int lane = lane_id();
-  const long base = (long)s * P.cap + ri;
+  const long base = slot_base(P, s) + ri;
   for (int pid = lane; pid < P.MU; pid += 64) {
     P.Q[base * P.MU + pid] = 0.0;
     if (P.E) P.E[base * P.MU + pid] = 0.0f;
@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(64) k_root(Problem P) {
     P.st_evals[s] = placeholder ? 0 : nroot * kNF * kNF;
     P.st_depth[s] = nroot - 1;
     if (P.born)
-      for (int h = 0; h < nroot; ++h) P.born[(long)s * P.cap + h] = h;
+      for (int h = 0; h < nroot; ++h) P.born[slot_base(P, s) + h] = h;
     P.flags[s] = P.seed_y ? kFlagSeed : 0;
     if (P.seed_y) P.seed_d[s] = D;
     P.state[s] = SLOT_ACTIVE;
@@ -787,7 +787,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
   const int lane = lane_id();
   const long leaf = P.sel[(long)s * P.bmax + r];
   const long nold = P.nleaf[s];
-  const long pbase = (long)s * P.cap + leaf;
+  const long pbase = slot_base(P, s) + leaf;
   const uint64_t pc = P.code[pbase];
   const double pkey = P.key[pbase];
   // delta of the container sums: minus the parent, plus its children
@@ -822,7 +822,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
     long ri = (ch == 0) ? leaf : nold + 3L * r + (ch - 1);
     const uint64_t cc = make_code(d + 1, 2 * ix + cx, 2 * iy + cy);
     if (P.born && lane == 0)  // the split is the container's st_splits-th (one per round)
-      P.born[(long)s * P.cap + ri] = (unsigned int)(1 + 4 * P.st_splits[s] + ch);
+      P.born[slot_base(P, s) + ri] = (unsigned int)(1 + 4 * P.st_splits[s] + ch);
     if ((skip >> ch) & 1) {
       store_zero<L>(P, s, ri, cc);
       wave_sync();
@@ -833,7 +833,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
         // box-basis pairs straight from the x-sums into the child's record
         // and the parent's delta, without staging them in LDS
         const double *G2 = S.g2b[ch], *G1 = S.g1b[ch];
-        const long base = (long)s * P.cap + ri;
+        const long base = slot_base(P, s) + ri;
         double part = 0.0;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
@@ -1103,7 +1103,7 @@ __device__ inline LpcItem lpc_item(const Problem &P, int w, int s0) {
   q.s = s;
   q.r = w - P.woff[s];
   q.leaf = P.sel[(long)s * P.bmax + q.r];
-  q.pbase = (long)s * P.cap + q.leaf;
+  q.pbase = slot_base(P, s) + q.leaf;
   q.pc = P.code[q.pbase];
   return q;
 }
@@ -1336,7 +1336,7 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
   const double wdt = kTwoPi * ldexp(1.0, -dd);
   const double fa = (0.25 * wdt) * (0.25 * wdt) / (4.0 * kPi * kPi);
   const long ri = (ch == 0) ? q.leaf : (long)P.nleaf[q.s] + 3L * q.r + (ch - 1);
-  const long base = (long)q.s * P.cap + ri;
+  const long base = slot_base(P, q.s) + ri;
   const long itm = (long)q.s * P.bmax + q.r;
   const bool head = valid && ch == 0;
   const double *par = (h ? PE : PQ) + it * lpc::kPairs;
