@@ -715,7 +715,10 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
                                c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
       std::vector<int> perm(n_params);
-      for (int r = 0; r < n_params; ++r) perm[r] = r;
+      for (int r = 0; r < n_params; ++r) {
+        perm[r] = r;
+        if (!(rsz[r] >= 0.0)) rsz[r] = 0.0;  // a model output that is not a number orders last
+      }
       std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return rsz[a] > rsz[b]; });
       HIPCHK(c, hipMemcpyAsync(c->rperm.p, perm.data(), sizeof(int) * n_params, hipMemcpyHostToDevice,
                                c->stream));
