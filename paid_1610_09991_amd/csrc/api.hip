@@ -56,7 +56,7 @@ struct paid_ctx {
   DevBuf code, key, Q, E;
   DevBuf slot_i, slot_d, sel, dv, de, dep, itau, errp, stl, counters, outs, errs;
   // learned seeding
-  DevBuf seedw, sfeat, sfold, sy, sact, pyr, seedd, ifill, labtmp, rowsz, rperm, movei;
+  DevBuf seedw, sfeat, sfold, sy, sact, pyr, seedd, ifill, labtmp, rowsz, rperm, movei, upart;
   bool seed_on = false;
   int seed_dmax = 8;
   double seed_kappa = 2.0;
@@ -454,7 +454,7 @@ void paid_destroy(paid_ctx *c) {
                     &c->errp,    &c->stl,  &c->counters, &c->outs, &c->errs,
                     &c->seedw,   &c->sfeat, &c->sfold, &c->sy,  &c->sact,  &c->pyr,
                     &c->seedd,   &c->ifill, &c->labtmp, &c->pairw, &c->born, &c->lcodes,
-                    &c->lq,      &c->rowsz, &c->rperm, &c->movei};
+                    &c->lq,      &c->rowsz, &c->rperm, &c->movei, &c->upart};
   for (DevBuf *b : bufs) b->release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -552,6 +552,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   HIPCHK(c, c->Q.ensure(sizeof(double) * regions * MU));
   if (store_E) HIPCHK(c, c->E.ensure(sizeof(float) * regions * MU));
   HIPCHK(c, c->movei.ensure(sizeof(int) * (size_t)(W + Wb + 1)));
+  HIPCHK(c, c->upart.ensure(sizeof(double) * update_scratch_doubles((int)W, MU)));
   HIPCHK(c, c->slot_i.ensure(sizeof(int) * (8 * W + 8)));
   HIPCHK(c, c->slot_d.ensure(sizeof(double) * (W * (size_t)MU + W)));
   HIPCHK(c, c->errp.ensure(sizeof(double) * W * (size_t)MU));
@@ -604,6 +605,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   P.Wb = (int)Wb;
   P.capb = capb;
   P.moveq = c->movei.as<int>();
+  P.upart = c->upart.as<double>();
   P.promo = P.moveq + W;
   P.bmin = bmin;
   P.bmax = bmax;

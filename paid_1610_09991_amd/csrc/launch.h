@@ -84,6 +84,7 @@ struct Problem {      // everything the round kernels need, passed by value
   double *dv;                 // [W*bmax*MU]
   double *de;                 // [W*bmax]
   double *dep;                // [W*bmax*MU] (when E != NULL)
+  double *upart;              // [W][chunks][2*MU + 2] chunk sums of the deltas
   long *st_rounds, *st_splits;  // [W]
   int *st_depth;              // [W]
   // queue and global counters
@@ -163,6 +164,8 @@ __device__ inline bool seed_split(const Problem &P, int s, uint64_t code) {
 }
 
 hipError_t launch_admit(const Problem &p, hipStream_t s);
+// doubles of the chunk sums of the per-parent deltas (Problem::upart)
+size_t update_scratch_doubles(int W, int MU);
 // moves of waiting containers from small to large slots (p.Wb > 0)
 hipError_t launch_move(const Problem &p, hipStream_t s);
 // predicted leaves of every parameter row (sum over its containers and cells

@@ -570,28 +570,68 @@ __global__ void k_admit(Problem P) {
   if (t == 0) *P.qhead = head < P.n_ctr ? head : P.n_ctr;
 }
 
-__global__ void __launch_bounds__(kSelThreads) k_update(Problem P) {
+// The per-parent deltas of a round, summed per container in a fixed order:
+// a container's k work items are split into up to kUpdChunks chunks of at
+// least kUpdMinRows consecutive items, each summed by its own workgroup
+// (k_update_part), and the chunk sums are added in chunk order (k_update).
+// With one chunk (k <= kUpdMinRows) the sums are those of one workgroup over
+// all the items.
+constexpr int kUpdChunks = 8, kUpdMinRows = 512;
+
+__device__ inline int upd_chunks(int k) {
+  const int c = (k + kUpdMinRows - 1) / kUpdMinRows;
+  return c < kUpdChunks ? c : kUpdChunks;
+}
+
+// one chunk's sums: [MU] values, [MU] per-pair errors, key delta, filled items
+__global__ void __launch_bounds__(kSelThreads) k_update_part(Problem P) {
   __shared__ double shd[2 * kSelThreads];
-  __shared__ double colv[kMaxMU], colp[kMaxMU];
+  const int s = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
+  if (s >= P.W) return;
+  const int k = P.selcnt[s], nch = upd_chunks(k);
+  if (c >= nch) return;
+  const int per = (k + nch - 1) / nch, r0 = c * per, r1 = r0 + per < k ? r0 + per : k;
+  const long it0 = (long)s * P.bmax + r0;
+  const long MU = P.MU;
+  double *part = P.upart + ((long)s * kUpdChunks + c) * (2 * MU + 2);
+  column_sums(P.dv + it0 * MU, r1 - r0, P.MU, part, shd);
+  if (P.dep) column_sums(P.dep + it0 * MU, r1 - r0, P.MU, part + MU, shd);
+  double de = 0.0, nf = 0.0;
+  for (int r = t; r < r1 - r0; r += blockDim.x) {
+    de += P.de[it0 + r];
+    nf += (double)P.ifill[it0 + r];
+  }
+  const double d = block_sum(de, shd);
+  const double fills = block_sum(nf, shd);
+  if (t == 0) {
+    part[2 * MU] = d;
+    part[2 * MU + 1] = fills;
+  }
+}
+
+__global__ void __launch_bounds__(kSelThreads) k_update(Problem P) {
   const int s = blockIdx.x, t = threadIdx.x;
   if (s >= P.W) return;
   const int k = P.selcnt[s];
   if (k == 0) return;
-  const long it0 = (long)s * P.bmax;
-  column_sums(P.dv + it0 * P.MU, k, P.MU, colv, shd);
-  if (P.dep) column_sums(P.dep + it0 * P.MU, k, P.MU, colp, shd);
-  for (int pid = t; pid < P.MU; pid += blockDim.x) {
-    P.val[(long)s * P.MU + pid] += colv[pid];
-    if (P.errp) P.errp[(long)s * P.MU + pid] += colp[pid];
+  const int nch = upd_chunks(k);
+  const long MU = P.MU;
+  const double *part = P.upart + (long)s * kUpdChunks * (2 * MU + 2);
+  for (long pid = t; pid < MU; pid += blockDim.x) {
+    double v = part[pid], e = part[MU + pid];
+    for (int c = 1; c < nch; ++c) {
+      v += part[c * (2 * MU + 2) + pid];
+      e += part[c * (2 * MU + 2) + MU + pid];
+    }
+    P.val[(long)s * MU + pid] += v;
+    if (P.errp) P.errp[(long)s * MU + pid] += e;
   }
-  double de = 0.0, nf = 0.0;
-  for (int r = t; r < k; r += blockDim.x) {
-    de += P.de[it0 + r];
-    nf += (double)P.ifill[it0 + r];
-  }
-  double d = block_sum(de, shd);
-  double fills = block_sum(nf, shd);
   if (t == 0) {
+    double d = part[2 * MU], fills = part[2 * MU + 1];
+    for (int c = 1; c < nch; ++c) {
+      d += part[c * (2 * MU + 2) + 2 * MU];
+      fills += part[c * (2 * MU + 2) + 2 * MU + 1];
+    }
     P.err[s] += d;
     P.st_evals[s] += (long)fills * (kNX * kNX);
     P.nleaf[s] += 3 * k;
@@ -798,9 +838,12 @@ hipError_t launch_worklist(const Problem &p, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_update(const Problem &p, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(p.W), dim3(kSelThreads), 0, s, p);
+  hipLaunchKernelGGL(k_update_part, dim3(p.W, kUpdChunks), dim3(kSelThreads), 0, s, p);
+  hipLaunchKernelGGL(k_update, dim3(p.W), dim3(64), 0, s, p);
   return hipGetLastError();
 }
+
+size_t update_scratch_doubles(int W, int MU) { return (size_t)W * kUpdChunks * (2 * (size_t)MU + 2); }
 hipError_t launch_finalize(const Problem &p, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(p.W), dim3(kSelThreads), 0, s, p);
   return hipGetLastError();
