@@ -74,7 +74,9 @@ struct paid_ctx {
   int max_J = 1;                 // rows of the largest table of the last build
   int lds_limit = 0;             // LDS bytes per workgroup (device attribute)
   float *noalloc = nullptr;      // this device's fixed working memory (paid_mlp_loss_grad_noalloc)
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // profile: around the evaluation launch
+  // profile: around the evaluation launch of the two rounds in flight
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  hipEvent_t evd[2] = {nullptr, nullptr};  // end of each of the two rounds in flight
 };
 
 namespace {
@@ -428,11 +430,17 @@ int paid_create(paid_ctx **out, const paid_config *cfg_in) {
     return fail(nullptr, PAID_ENOMEM, "pinned counters: %s", hipGetErrorString(e));
   }
   if (cfg.profile) {
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->ev2) != hipSuccess || hipEventCreate(&c->ev3) != hipSuccess) {
       paid_destroy(c);
       return fail(nullptr, PAID_EDEVICE, "hipEventCreate failed");
     }
   }
+  for (int k = 0; k < 2; ++k)
+    if (hipEventCreateWithFlags(&c->evd[k], hipEventDisableTiming) != hipSuccess) {
+      paid_destroy(c);
+      return fail(nullptr, PAID_EDEVICE, "hipEventCreate failed");
+    }
   int rc = ensure_rule(c);
   if (rc == PAID_OK) rc = ensure_noalloc(c);
   if (rc != PAID_OK) {
@@ -457,8 +465,8 @@ void paid_destroy(paid_ctx *c) {
                     &c->lq,      &c->rowsz, &c->rperm, &c->movei, &c->upart};
   for (DevBuf *b : bufs) b->release();
   if (c->host_counters) (void)hipHostFree(c->host_counters);
-  if (c->ev0) (void)hipEventDestroy(c->ev0);
-  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t ev : {c->ev0, c->ev1, c->ev2, c->ev3, c->evd[0], c->evd[1]})
+    if (ev) (void)hipEventDestroy(ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -755,7 +763,8 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   double eval_ms = 0.0;
   // one device round in three parts: admission, roots, selection and work
   // list; evaluation; updates, finalisation and the read-back of the three
-  // counters the host needs
+  // counters the host needs (into one of two pinned buffers: parts 2 and 3
+  // are the third part with buffer 0 and 1)
   auto part = [&](int k, hipStream_t st) -> hipError_t {
     hipError_t e;
     if (k == 0) {
@@ -768,21 +777,21 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
     if (k == 1) return launch_eval(P, eval_grid, st);
     if ((e = launch_update(P, st)) != hipSuccess) return e;
     if ((e = launch_finalize(P, st)) != hipSuccess) return e;
-    return hipMemcpyAsync(c->host_counters, cnt + 4, 12, hipMemcpyDeviceToHost, st);
+    return hipMemcpyAsync(c->host_counters + 4 * (k - 2), cnt + 4, 12, hipMemcpyDeviceToHost, st);
   };
   // with cfg.graph each part is captured once and replayed every round (the
   // arguments of every launch are the same in every round); the profiling
   // events are recorded between the parts, outside the graphs
-  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
   struct GraphGuard {
     hipGraphExec_t *ge;
     ~GraphGuard() {
-      for (int k = 0; k < 3; ++k)
+      for (int k = 0; k < 4; ++k)
         if (ge[k]) (void)hipGraphExecDestroy(ge[k]);
     }
   } gguard{gexec};
   if (cfg.graph) {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       hipGraph_t g = nullptr;
       HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
       hipError_t e1 = part(k, c->stream);
@@ -799,24 +808,42 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   auto run_part = [&](int k) -> hipError_t {
     return gexec[k] ? hipGraphLaunch(gexec[k], c->stream) : part(k, c->stream);
   };
-  for (;;) {
-    HIPCHK(c, run_part(0));
-    if (cfg.profile) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, run_part(1));
-    if (cfg.profile) HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-    HIPCHK(c, run_part(2));
+  // Two rounds in flight: round r + 1 is queued before the host reads the
+  // counters of round r, so the device does not wait for the host between
+  // rounds.  A round queued after the last one finds nothing to do (no
+  // container left to admit, select or update).
+  hipEvent_t evb[2] = {c->ev0, c->ev2}, eve[2] = {c->ev1, c->ev3};
+  auto launch_round = [&](int buf) -> hipError_t {
+    hipError_t e;
+    if ((e = run_part(0)) != hipSuccess) return e;
+    if (cfg.profile && (e = hipEventRecord(evb[buf], c->stream)) != hipSuccess) return e;
+    if ((e = run_part(1)) != hipSuccess) return e;
+    if (cfg.profile && (e = hipEventRecord(eve[buf], c->stream)) != hipSuccess) return e;
+    if ((e = run_part(2 + buf)) != hipSuccess) return e;
+    return hipEventRecord(c->evd[buf], c->stream);
+  };
+  HIPCHK(c, launch_round(0));
+  int last = 0;  // buffer of the last round read
+  for (long r = 0;; ++r) {
+    const int buf = (int)(r & 1);
+    HIPCHK(c, launch_round(buf ^ 1));
+    HIPCHK(c, hipEventSynchronize(c->evd[buf]));
+    const int *hc = c->host_counters + 4 * buf;
+    last = buf;
     ++rounds;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    eval_items += c->host_counters[2];
+    eval_items += hc[2];
     if (cfg.profile) {
       float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      HIPCHK(c, hipEventElapsedTime(&ms, evb[buf], eve[buf]));
       eval_ms += ms;
     }
-    if (c->host_counters[0] >= n_ctr) break;
-    if (rounds > 4L * capb + 64L * (n_ctr / Ws + 1))
+    if (hc[0] >= n_ctr) break;
+    if (rounds > 4L * capb + 64L * (n_ctr / Ws + 1)) {
+      (void)hipStreamSynchronize(c->stream);
       return fail(c, PAID_EINTERNAL, "round loop did not finish (%ld rounds)", rounds);
+    }
   }
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // the round queued after the last
   if (!out_dev) HIPCHK(c, hipMemcpyAsync(out, c->outs.p, out_bytes, hipMemcpyDeviceToHost, c->stream));
   if (err_out && !err_dev)
     HIPCHK(c, hipMemcpyAsync(err_out, c->errs.p, out_bytes, hipMemcpyDeviceToHost, c->stream));
@@ -833,7 +860,7 @@ int paid_integrate(paid_ctx *c, const paid_params *params, int n_params, const d
   long long gs[5] = {0, 0, 0, 0, 0};
   HIPCHK(c, hipMemcpyAsync(gs, P.gstats, sizeof gs, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  const int notconv = c->host_counters[1];
+  const int notconv = c->host_counters[4 * last + 1];
   if (stats) {
     memset(stats, 0, sizeof *stats);
     stats->containers = n_ctr;
