@@ -49,3 +49,18 @@ def test_create_without_a_device_reports_it():
     with pytest.raises(P.PaidError) as ei:
         P.Context()
     assert ei.value.code == P.EDEVICE and "device" in str(ei.value)
+
+
+def test_key_histogram_fixed_point_cannot_overflow():
+    """The leaf selection adds keys as fixed-point integers scaled by
+    2^(62 - ceil(log2 n)) / maxkey (n leaves, maxkey the largest key): n keys
+    of at most maxkey, each truncated as on the device, sum to at most
+    2^62 (1 + 2^-50) < 2^63 for every leaf count a region code allows
+    (the same arithmetic as the kernel, in Python integers)."""
+    import math
+    for n in [1, 2, 3, 4, 5, 1000, 2 ** 24, 2 ** 24 + 1, 2 ** 28 - 1, 2 ** 28]:
+        lgn = (n - 1).bit_length() if n > 1 else 0
+        for maxkey in [1e-300, 1e-10, 0.3, 1.0, 3.7e5, 1e300]:
+            scale = math.ldexp(1.0, 62 - lgn) / maxkey
+            largest = int(maxkey * scale)  # the largest key's fixed-point value
+            assert largest * n <= 2 ** 62 * (1 + 2 ** -50) < 2 ** 63, (n, maxkey)
