@@ -367,10 +367,15 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     hsum[b] = 0ull;
   }
   __syncthreads();
-  // fixed-point scale 2^(62 - ceil(log2 n)) / maxkey: n keys of at most maxkey
-  // sum to at most 2^62, so no bin, prefix or deficit overflows 64 bits
+  // fixed-point value of a key k: (k 2^-ke) * scale with ke = ilogb(maxkey) and
+  // scale = 2^(62 - ceil(log2 n)) / (maxkey 2^-ke), i.e. k 2^(62 - ceil(log2 n)) /
+  // maxkey with the power of two applied apart, so that the scale stays finite
+  // for a subnormal maxkey. n keys of at most maxkey sum to at most 2^62, so no
+  // bin, prefix or deficit overflows 64 bits.
   const int lgn = n > 1 ? 64 - __clzll((unsigned long long)(n - 1)) : 0;
-  const double scale = maxkey > 0.0 ? ldexp(1.0, 62 - lgn) / maxkey : 0.0;
+  const bool kfin = maxkey > 0.0 && isfinite(maxkey);
+  const int ke = kfin ? ilogb(maxkey) : 0;
+  const double scale = kfin ? ldexp(1.0, 62 - lgn) / ldexp(maxkey, -ke) : 0.0;
   {
     long i = t;
     for (; i + 3 * st < n; i += 4 * st) {
@@ -381,14 +386,14 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
       for (int j = 0; j < 4; ++j) {
         const int b = key_bin(k[j], eb);
         atomicAdd(&hcnt[b], 1u);
-        atomicAdd(&hsum[b], (unsigned long long)(k[j] * scale));
+        atomicAdd(&hsum[b], (unsigned long long)(ldexp(k[j], -ke) * scale));
       }
     }
     for (; i < n; i += st) {
       const double k = P.key[base + i];
       const int b = key_bin(k, eb);
       atomicAdd(&hcnt[b], 1u);
-      atomicAdd(&hsum[b], (unsigned long long)(k * scale));
+      atomicAdd(&hsum[b], (unsigned long long)(ldexp(k, -ke) * scale));
     }
   }
   __syncthreads();
@@ -412,7 +417,7 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     }
     unsigned int cex = cinc - c8;
     unsigned long long sex = sinc - s8;
-    double dd = deficit * scale;
+    double dd = ldexp(deficit, -ke) * scale;
     unsigned long long dfix = dd >= 4.0e18 ? 4000000000000000000ull : (unsigned long long)(dd > 0 ? dd : 0.0);
     int beps = (P.err_mode != 1) ? key_bin(eps, eb) : 0;
     if (P.err_mode != 1 && eps >= maxkey) beps = -1;  // no single leaf exceeds eps

@@ -52,15 +52,28 @@ def test_create_without_a_device_reports_it():
 
 
 def test_key_histogram_fixed_point_cannot_overflow():
-    """The leaf selection adds keys as fixed-point integers scaled by
-    2^(62 - ceil(log2 n)) / maxkey (n leaves, maxkey the largest key): n keys
-    of at most maxkey, each truncated as on the device, sum to at most
-    2^62 (1 + 2^-50) < 2^63 for every leaf count a region code allows
-    (the same arithmetic as the kernel, in Python integers)."""
+    """The leaf selection adds keys as fixed-point integers k 2^(62 - ceil(log2 n))
+    / maxkey (n leaves, maxkey the largest key), formed as (k 2^-e) * scale with
+    e = ilogb(maxkey) so that the scale is finite for every positive finite
+    maxkey, subnormal ones included: n keys of at most maxkey, each truncated
+    as on the device, sum to at most 2^62 (1 + 2^-50) < 2^63 for every leaf
+    count a region code allows (the same arithmetic as the kernel, in Python)."""
     import math
+    import sys
+    tiny = math.ldexp(1.0, -1074)
     for n in [1, 2, 3, 4, 5, 1000, 2 ** 24, 2 ** 24 + 1, 2 ** 28 - 1, 2 ** 28]:
         lgn = (n - 1).bit_length() if n > 1 else 0
-        for maxkey in [1e-300, 1e-10, 0.3, 1.0, 3.7e5, 1e300]:
-            scale = math.ldexp(1.0, 62 - lgn) / maxkey
-            largest = int(maxkey * scale)  # the largest key's fixed-point value
+        for maxkey in [tiny, 3 * tiny, 1e-310, 1e-300, 1e-10, 0.3, 1.0, 3.7e5,
+                       1e300, sys.float_info.max]:
+            e = math.frexp(maxkey)[1] - 1  # ilogb
+            scale = math.ldexp(1.0, 62 - lgn) / math.ldexp(maxkey, -e)
+            assert math.isfinite(scale), (n, maxkey)
+            for k in [maxkey, maxkey * 0.999, maxkey / 3, tiny, 0.0]:
+                v = math.ldexp(k, -e) * scale
+                assert math.isfinite(v) and v <= math.ldexp(1.0, 62 - lgn) * (1 + 2 ** -50)
+            largest = int(math.ldexp(maxkey, -e) * scale)
             assert largest * n <= 2 ** 62 * (1 + 2 ** -50) < 2 ** 63, (n, maxkey)
+            # the split leaves the normal-range value unchanged
+            if maxkey >= 1e-290 and maxkey <= 1e290:
+                assert math.ldexp(maxkey / 3, -e) * scale == \
+                    (maxkey / 3) * (math.ldexp(1.0, 62 - lgn) / maxkey), (n, maxkey)
