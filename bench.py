@@ -63,8 +63,8 @@ K_FLOPS_PER_NODE = 80
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2505
-TRAFFIC_SOURCES_SHA256 = "629a06c382e7eb9ad37834c05d18529cedecdc8d6c6c904dd25db1cecc5106c6"
+TRAFFIC_BYTES_PER_ITEM = 2507
+TRAFFIC_SOURCES_SHA256 = "5c17a35af85371b1b34137801621530000a2895b8b7ae83ad87eaf1b403a6263"
 NODES_PER_ITEM = 289
 
 # Per-workload region budget (max_regions): the smallest power of two that

@@ -67,7 +67,11 @@ enum {
                                 max(atol, rtol * sum over pairs |value|)  (the
                                 paper's global criterion) */
   PAID_ERR_PER_INTEGRAL = 1, /* every pair: sum over leaves of its error <=
-                                max(atol, rtol * max(|value_pq|, nu max |value|)) */
+                                max(atol, rtol * max(|value_pq|, nu max |value|));
+                                per-leaf errors are kept in FP32, positive ones
+                                never below FLT_MIN, so a pair whose tolerance is
+                                below FP32's normal range (|value| ~ 1e-30 and
+                                less) ends PAID_ENOCONV rather than passing */
   PAID_ERR_WEIGHTED = 2      /* the global test with pair weights w (set with
                                 paid_set_pair_weights): sum over leaves and pairs
                                 of w |Q_N - Q_2N| <= max(atol, rtol * sum w |value|);

@@ -110,6 +110,15 @@ __device__ inline int tab_index(const Entry &e, double ax) {
   return j < e.J - 1 ? j : e.J - 1;
 }
 
+// FP32 copy of a per-pair error estimate (the stored E and the running sums
+// built from it): rounded to nearest, except that a positive estimate below
+// the smallest normal float is kept as that float, an upper bound, instead of
+// flushing towards zero and passing a tolerance it does not meet.
+__device__ inline float err_f32(double e) {
+  const float f = (float)e;
+  return (e > 0.0 && f < 1.17549435e-38f) ? 1.17549435e-38f : f;
+}
+
 // n / d for a normal, non-zero d: the hardware reciprocal estimate refined by
 // two Newton-Raphson steps, then one residual correction of the quotient
 // (Markstein's scheme); no scaling for extreme exponents, which the far

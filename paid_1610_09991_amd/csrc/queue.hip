@@ -207,7 +207,8 @@ __device__ int tolerance_test(const Problem &P, int s, double *shd, double &eps,
     } else if (e > tau * (1.0 - kResumMargin)) {
       near = 1;
     }
-    P.itau[(long)s * P.MU + pid] = (float)(tau > 0.0 ? 1.0 / tau : 0.0);
+    // FP32 weight, held at the largest float where tau is below FP32's range
+    P.itau[(long)s * P.MU + pid] = (float)(tau > 0.0 ? fmin(1.0 / tau, 3.4028234663852886e38) : 0.0);
   }
   double excess = block_sum(ex, shd);
   double nbad = block_sum((double)bad, shd);
@@ -360,40 +361,43 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     for (; i < n; i += st) m0 = fmax(m0, P.key[base + i]);
   }
   const double maxkey = block_max(fmax(fmax(m0, m1), fmax(m2, m3)), shd);
-  const int eb = (int)(__double_as_longlong(maxkey > 0.0 ? maxkey : 1.0) >> 50);
+  // keys are binned and summed as k 2^-ke with ke = ilogb(maxkey): the same
+  // bins as k itself wherever both are normal, and bins a quarter octave wide
+  // also for keys in the subnormal range (whose raw exponent bits are zero)
+  const bool kfin = maxkey > 0.0 && isfinite(maxkey);
+  const int ke = kfin ? ilogb(maxkey) : 0;
+  const int eb = (int)(__double_as_longlong(maxkey > 0.0 ? ldexp(maxkey, -ke) : 1.0) >> 50);
   // pass 2: histogram of counts and fixed-point sums (exact, order-free)
   for (int b = t; b < kBins; b += blockDim.x) {
     hcnt[b] = 0u;
     hsum[b] = 0ull;
   }
   __syncthreads();
-  // fixed-point value of a key k: (k 2^-ke) * scale with ke = ilogb(maxkey) and
-  // scale = 2^(62 - ceil(log2 n)) / (maxkey 2^-ke), i.e. k 2^(62 - ceil(log2 n)) /
-  // maxkey with the power of two applied apart, so that the scale stays finite
-  // for a subnormal maxkey. n keys of at most maxkey sum to at most 2^62, so no
+  // fixed-point value of a key k: (k 2^-ke) * scale with scale =
+  // 2^(62 - ceil(log2 n)) / (maxkey 2^-ke), i.e. k 2^(62 - ceil(log2 n)) / maxkey
+  // with the power of two applied apart, so that the scale stays finite for a
+  // subnormal maxkey. n keys of at most maxkey sum to at most 2^62, so no
   // bin, prefix or deficit overflows 64 bits.
   const int lgn = n > 1 ? 64 - __clzll((unsigned long long)(n - 1)) : 0;
-  const bool kfin = maxkey > 0.0 && isfinite(maxkey);
-  const int ke = kfin ? ilogb(maxkey) : 0;
   const double scale = kfin ? ldexp(1.0, 62 - lgn) / ldexp(maxkey, -ke) : 0.0;
   {
     long i = t;
     for (; i + 3 * st < n; i += 4 * st) {
       double k[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) k[j] = P.key[base + i + j * st];
+      for (int j = 0; j < 4; ++j) k[j] = ldexp(P.key[base + i + j * st], -ke);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int b = key_bin(k[j], eb);
         atomicAdd(&hcnt[b], 1u);
-        atomicAdd(&hsum[b], (unsigned long long)(ldexp(k[j], -ke) * scale));
+        atomicAdd(&hsum[b], (unsigned long long)(k[j] * scale));
       }
     }
     for (; i < n; i += st) {
-      const double k = P.key[base + i];
+      const double k = ldexp(P.key[base + i], -ke);
       const int b = key_bin(k, eb);
       atomicAdd(&hcnt[b], 1u);
-      atomicAdd(&hsum[b], (unsigned long long)(ldexp(k, -ke) * scale));
+      atomicAdd(&hsum[b], (unsigned long long)(k * scale));
     }
   }
   __syncthreads();
@@ -419,7 +423,7 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     unsigned long long sex = sinc - s8;
     double dd = ldexp(deficit, -ke) * scale;
     unsigned long long dfix = dd >= 4.0e18 ? 4000000000000000000ull : (unsigned long long)(dd > 0 ? dd : 0.0);
-    int beps = (P.err_mode != 1) ? key_bin(eps, eb) : 0;
+    int beps = (P.err_mode != 1) ? key_bin(ldexp(eps, -ke), eb) : 0;
     if (P.err_mode != 1 && eps >= maxkey) beps = -1;  // no single leaf exceeds eps
     // first bin b (in this lane's 8) meeting all conditions
     int found = kBins, fcnt = 0;
@@ -494,7 +498,7 @@ __global__ void __launch_bounds__(kSelThreads) k_select(Problem P) {
     int isp[4], full[4], np = 0, nf = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int bin = (i0 + j < n) ? key_bin(P.key[base + i0 + j], eb) : kBins;
+      const int bin = (i0 + j < n) ? key_bin(ldexp(P.key[base + i0 + j], -ke), eb) : kBins;
       isp[j] = (bin == bpart && i0 + j < n) ? 1 : 0;
       full[j] = (bin <= bfull && i0 + j < n) ? 1 : 0;
       np += isp[j];

@@ -568,7 +568,7 @@ __device__ double store_region(WaveLds<L> &S, const Problem &P, int s, long ri, 
   for (int pid = lane; pid < P.MU; pid += 64) {
     double q = S.cq[pid], e = fabs(S.ce[pid]);
     P.Q[base * P.MU + pid] = q;
-    if (P.E) P.E[base * P.MU + pid] = (float)e;
+    if (P.E) P.E[base * P.MU + pid] = err_f32(e);
     part += (P.err_mode != 0) ? e * (double)P.itau[(long)s * P.MU + pid] : e;
   }
   double key = wave_sum(part);
@@ -741,7 +741,7 @@ __global__ void __launch_bounds__(64) k_root(Problem P) {
       key += store_region<L>(S, P, s, h, P.sym ? make_code(1, h, 1) : make_code(0, 0, 0));
       for (int pid = threadIdx.x; pid < P.MU; pid += 64) {
         const long o = (long)s * P.MU + pid;
-        const double e = (double)(float)fabs(S.ce[pid]);
+        const double e = (double)err_f32(fabs(S.ce[pid]));
         P.val[o] = h ? P.val[o] + S.cq[pid] : S.cq[pid];
         if (P.errp) P.errp[o] = h ? P.errp[o] + e : e;
       }
@@ -844,10 +844,10 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
             if (P.sym) f = podd[pid] ? 0.0 : 2.0 * fa;
             const double q2 = G2[jk], q = f * q2, e = fabs(f * (q2 - G1[jk]));
             P.Q[base * MU + pid] = q;
-            if (P.E) P.E[base * MU + pid] = (float)e;
+            if (P.E) P.E[base * MU + pid] = err_f32(e);
             part += (P.err_mode != 0) ? e * (double)P.itau[(long)s * MU + pid] : e;
             dv[k] += q;
-            dp[k] += (double)(float)e;
+            dp[k] += (double)err_f32(e);
           }
         }
         const double key = wave_sum(part);
@@ -869,7 +869,7 @@ __device__ void do_item(WaveLds<L> &S, const Problem &P, const int *pidmap, cons
         dv[k] += S.cq[pid];
         // the same float-rounded value that is stored and later subtracted,
         // so the running per-pair error sums carry no rounding residue
-        dp[k] += (double)(float)fabs(S.ce[pid]);
+        dp[k] += (double)err_f32(fabs(S.ce[pid]));
       }
     }
     wave_sync();
@@ -1356,7 +1356,7 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
     }
     const double x = phc ? 0.0 : fa * v;  // lane 0: Q_2N of the pair, lane 1: E
     const double e = fabs(x);
-    const float ef = (float)e;
+    const float ef = err_f32(e);
     key += wgt ? e * wgt[p] : e;
     if (h == 0) {
       if (valid) P.Q[base * MU + p] = x;

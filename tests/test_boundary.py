@@ -77,3 +77,34 @@ def test_key_histogram_fixed_point_cannot_overflow():
             if maxkey >= 1e-290 and maxkey <= 1e290:
                 assert math.ldexp(maxkey / 3, -e) * scale == \
                     (maxkey / 3) * (math.ldexp(1.0, 62 - lgn) / maxkey), (n, maxkey)
+
+
+
+def test_key_bins_stay_a_quarter_octave_wide_below_the_normal_range():
+    """The leaf selection bins a key k by the exponent and top two mantissa
+    bits of k 2^-e (e = ilogb of the largest key), four bins per octave below
+    the largest key.  Scaled this way, keys 2^-j times the largest land in bin
+    4j also where k itself is subnormal (raw exponent bits zero), and bins of
+    normal keys are those of the unscaled bits (the same arithmetic as the
+    kernel, in Python)."""
+    import math
+    import struct
+
+    def bits(x):
+        return struct.unpack("<q", struct.pack("<d", x))[0]
+
+    def key_bin(k, eb):
+        if not k > 0.0:
+            return 511
+        return min(max(eb - (bits(k) >> 50), 0), 511)
+
+    for maxkey in [1e-300, 3e-305, math.ldexp(1.0, -1060), 0.7, 1e300]:
+        e = math.frexp(maxkey)[1] - 1
+        eb = bits(math.ldexp(maxkey, -e)) >> 50
+        for jj in range(0, 127):
+            k = math.ldexp(maxkey, -jj)
+            if k == 0.0 or math.ldexp(k, jj) != maxkey:
+                break  # below the smallest subnormal
+            assert key_bin(math.ldexp(k, -e), eb) == 4 * jj, (maxkey, jj)
+            if k >= 2.3e-308 and maxkey >= 2.3e-308:
+                assert key_bin(k, bits(maxkey) >> 50) == 4 * jj

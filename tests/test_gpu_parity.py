@@ -235,6 +235,33 @@ def test_unit_and_gaussian_integrands(P):
         assert abs(out[0, 0, 0, 0, 0] - exact) <= e[0, 0, 0, 0, 0] + 1e-16
 
 
+def test_integrand_at_the_bottom_of_the_double_range(P):
+    """A wide Gaussian centred 37 widths outside the zone: values ~1e-297,
+    integral ~2e-299, leaf errors (the keys of the leaf selection) far below
+    ~2.6e-290, where 2^62 / (largest key) is not a finite double.  The global
+    mode still meets rtol 1e-10 against the closed form; the per-integral mode,
+    whose per-leaf errors are FP32, must end ENOCONV (its tolerance ~2e-309 is
+    below FP32's range) instead of passing on errors rounded to zero."""
+    from scipy import special
+    x0, y0, s = math.pi + 370.0, 0.0, 10.0
+    f = lambda cc: special.ndtr((math.pi - cc) / s) - special.ndtr((-math.pi - cc) / s)
+    exact = 2 * math.pi * s * s * f(x0) * f(y0) / (4 * math.pi ** 2)
+    assert 1e-300 < exact < 1e-298
+    args = ([[1, 0, 0, 0.1, 0.1]], [[0.0, 0.0]], W.ff_box(0), 0)
+    with P.Context(kind=P.GAUSS, gauss=(x0, y0, s), max_regions=1 << 14) as c:
+        out, e, st, rc = c.integrate(*args, channels=P.PH, rtol=1e-10, err=True)
+    print("global", rc, st, out[0, 0, 0, 0, 0], exact, flush=True)
+    assert rc == P.OK
+    assert abs(out[0, 0, 0, 0, 0] - exact) <= 1e-10 * exact
+    assert abs(out[0, 0, 0, 0, 0] - exact) <= e[0, 0, 0, 0, 0] + 1e-310
+    with P.Context(kind=P.GAUSS, gauss=(x0, y0, s), err_mode=P.ERR_PER_INTEGRAL,
+                   max_regions=1 << 10) as c:
+        out, e, st, rc = c.integrate(*args, channels=P.PH, rtol=1e-10, err=True)
+    print("per integral", rc, st, flush=True)
+    assert rc == P.ENOCONV and st["not_converged"] == 1
+    assert np.isfinite(out).all()
+
+
 def test_per_integral_mode(P):
     p = np.array([[1.0, -0.25, -0.95, 0.05, 0.2]])
     q = np.array([[1.57, 1.31]])
