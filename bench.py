@@ -145,11 +145,33 @@ def cpu_baseline(cfg, budget_s: float, threads: int, seed: int = 11, nq: int = 4
                                       nthreads=threads)
     dt = time.perf_counter() - t0
     n_int = len(conts) * M * (M + 1) // 2
+    # the serial algorithm on one core: every 16th container of the same sample
+    one = conts[::16]
+    t1 = time.perf_counter()
+    O.integrate_batch(one, rtol=cfg["rtol"], err_mode=O.ERR_GLOBAL, batch=1, nthreads=1)
+    d1 = time.perf_counter() - t1
     return {"value": n_int / dt, "unit": "integrals/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(conts)} containers of the same workload ({len(rows)} parameter rows "
                       f"x {nq} seeded q x 2 channels), serial Alg. 2 per container, OpenMP over "
                       f"containers, {dt:.1f} s wall, budget {budget_s:.0f} s",
-            "seconds": dt}
+            "seconds": dt, "host_cpu": host_cpu(),
+            "single_thread": {"value": len(one) * M * (M + 1) // 2 / d1, "unit": "integrals/s",
+                              "cores": 1, "sample": f"every 16th container of the sample "
+                                                    f"({len(one)}), {d1:.1f} s"}}
+
+
+def host_cpu() -> str:
+    """Model name of the host processor (from /proc/cpuinfo) and its thread count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name}, {os.cpu_count()} threads visible"
 
 
 class Runner:

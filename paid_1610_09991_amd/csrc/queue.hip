@@ -201,7 +201,7 @@ __device__ int tolerance_test(const Problem &P, int s, double *shd, double &eps,
     double v = fabs(P.val[(long)s * P.MU + pid]);
     double tau = fmax(P.atol, P.rtol * fmax(v, P.nu * vmax));
     double e = P.errp[(long)s * P.MU + pid];
-    if (e > tau) {
+    if (!(e <= tau)) {  // a NaN error fails the test
       bad = 1;
       ex += (e - tau) / tau;
     } else if (e > tau * (1.0 - kResumMargin)) {
