@@ -224,9 +224,10 @@ class Runner:
                   f"{sum(s['regions'] for s in sts)}", file=sys.stderr, flush=True)
         self.torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats = []
+        stats, ends = [], []
         for i in range(steps):
-            sts = self.one_step(per_scale)
+            sts = self.one_step(per_scale)  # each call returns after its stream is idle
+            ends.append(time.perf_counter())
             stats += sts
             print(f"# {tag} step {i}: {sum(s['seconds'] for s in sts):.3f} s, regions "
                   f"{sum(s['regions'] for s in sts)}, evals {sum(s['kernel_evals'] for s in sts):.4g}",
@@ -235,7 +236,9 @@ class Runner:
         dt = time.perf_counter() - t0
         per_step = len(stats) // steps
         last = stats[-per_step:]
+        step_s = np.diff(np.array([t0] + ends))
         return {"value": self.n_int * steps / dt, "ms_per_step": 1e3 * dt / steps,
+                "median_ms_per_step": float(1e3 * np.median(step_s)),
                 "steps": steps, "warmup": warmup,
                 "regions": sum(s["regions"] for s in last),
                 "kernel_evals": sum(s["kernel_evals"] for s in last),
