@@ -40,3 +40,14 @@ def test_half_zone_variant_counts_only_computed_pairs():
     assert bench.computed_pairs(W.config("C2")["ff"], 1) == 25
     assert bench.computed_pairs(W.config("C1")["ff"], 1) == 9
     assert bench.computed_pairs(W.config("C4")["ff"], 2) == 169
+
+
+def test_cpu_baseline_reports_both_oracle_rates():
+    """The oracle's rate on the host: OpenMP over containers and one core
+    (the serial algorithm), with the sample and the host processor named."""
+    import workloads as W
+    cfg = W.config("C1")
+    r = bench.cpu_baseline(cfg, 5.0, 2, nq=1, max_rows=1)
+    assert r["kind"] == "oracle" and r["cores"] == 2 and r["value"] > 0
+    assert r["single_thread"]["cores"] == 1 and r["single_thread"]["value"] > 0
+    assert "threads visible" in r["host_cpu"]
