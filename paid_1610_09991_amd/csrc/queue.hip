@@ -627,13 +627,14 @@ __global__ void __launch_bounds__(kSelThreads) k_update(Problem P) {
   const long MU = P.MU;
   const double *part = P.upart + (long)s * kUpdChunks * (2 * MU + 2);
   for (long pid = t; pid < MU; pid += blockDim.x) {
-    double v = part[pid], e = part[MU + pid];
-    for (int c = 1; c < nch; ++c) {
-      v += part[c * (2 * MU + 2) + pid];
-      e += part[c * (2 * MU + 2) + MU + pid];
-    }
+    double v = part[pid];
+    for (int c = 1; c < nch; ++c) v += part[c * (2 * MU + 2) + pid];
     P.val[(long)s * MU + pid] += v;
-    if (P.errp) P.errp[(long)s * MU + pid] += e;
+    if (P.dep) {  // per-pair error sums are kept where the deltas carry them
+      double e = part[MU + pid];
+      for (int c = 1; c < nch; ++c) e += part[c * (2 * MU + 2) + MU + pid];
+      P.errp[(long)s * MU + pid] += e;
+    }
   }
   if (t == 0) {
     double d = part[2 * MU], fills = part[2 * MU + 1];
