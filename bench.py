@@ -44,11 +44,15 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64: vector (256 CUs x 4 SIMD x 16 lanes x 2 
 # Algorithmic work of one region-evaluation work item (a parent and its four
 # children, rule pair N = 4 / 2N = 8, shared 17 x 17 node grid), in FP64 flops
 # (an FMA counts 2):
-#   integrand: 289 nodes x 80 (dispersion 12, close-pair switch 8, interval
-#              arguments 4, two Horner chains of degree 13 = 52, combine 4);
-#              a node needs two chains (two values, or one value and its
-#              divided difference); the third chain that the branch-free
-#              evaluation computes and discards is not counted;
+#   integrand: 289 nodes x 72 (dispersion 4, close-pair switch 8, interval
+#              arguments 4, two Horner chains of degree 13 = 52, combine 4),
+#              plus 17 node columns x 8: along a column the two energies
+#              are affine in the row's cosine, -2t (cx + cy) - 4t' cx cy - mu
+#              = (-2t cx - mu) + cy (-2t - 4t' cx), i.e. 2 FMAs per column
+#              and energy and one FMA per node and energy; a node needs two
+#              chains (two values, or one value and its divided
+#              difference); the third chain that the branch-free evaluation
+#              computes and discards is not counted;
 #   separable projection with NP = NB(NB+1)/2 axis products, NB = 2L+1:
 #     y-sums  2 x 17 x NP x 27 (fine: 9 mul + 9 FMA) + 2 x 9 x NP x 10 (coarse: 5 FMA)
 #     x-sums  4 children x NP^2 x 42 (fine 9 x (mul + FMA), coarse 5 x (mul + FMA))
@@ -57,14 +61,16 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64: vector (256 CUs x 4 SIMD x 16 lanes x 2 
 # This is the method's work; an implementation that forms the same sums in
 # fewer operations (another basis of the axis products, edges evaluated once
 # per child) is credited with this count, not with its own.
-K_FLOPS_PER_NODE = 80
+K_FLOPS_PER_NODE = 72
+COLUMNS_PER_ITEM = 17
+K_FLOPS_PER_COLUMN = 8
 
 # HBM bytes per work item of the region-evaluation kernel, from the
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2507
-TRAFFIC_SOURCES_SHA256 = "5c17a35af85371b1b34137801621530000a2895b8b7ae83ad87eaf1b403a6263"
+TRAFFIC_BYTES_PER_ITEM = 2514
+TRAFFIC_SOURCES_SHA256 = "bfa2bc60968e32d0703060ed8653636d7f8c476e52c6af189c636ba0f9c993b9"
 NODES_PER_ITEM = 289
 
 # Per-workload region budget (max_regions): the smallest power of two that
@@ -94,7 +100,7 @@ def kernel_sources_sha256() -> str:
 
 
 def item_flops(M: int, L: int, separable: bool) -> int:
-    k = NODES_PER_ITEM * K_FLOPS_PER_NODE
+    k = NODES_PER_ITEM * K_FLOPS_PER_NODE + COLUMNS_PER_ITEM * K_FLOPS_PER_COLUMN
     if not separable:
         return k + 4 * 2 * M * M * (81 + 25)
     nb = 2 * L + 1

@@ -99,14 +99,18 @@ __host__ __device__ inline uint64_t code_iy(uint64_t c) { return c & 0xFFFFFFFul
 
 // ---------------------------------------------------------------------------
 // Frequency-sum table evaluation.
-// interval of |x| (no transcendental: exponent and top mantissa bits of |x|/w).
-// Both candidates are formed and one is selected, without a branch; for
-// v >= 1 the bits above the top log2(P) mantissa bits are (exponent << log2(P) | m).
+// interval of |x| (no transcendental: exponent and top mantissa bits of
+// v = |x|/w).  Central intervals: jc = round(P v), at most P; octave
+// intervals from the high word of v, whose bits above the top log2(P)
+// mantissa bits are (exponent << log2(P) | m).  For v < 1 the octave index
+// is at most jc and for v >= 1 at least P + 1 > jc, so the larger of the
+// two is the interval: no compare or select.
 __device__ inline int tab_index(const Entry &e, double ax) {
-  const float v = (float)(ax * e.inv_w);
-  const int jc = (int)fmaf(fminf(v, 1.0f), (float)kTabPerOct, 0.5f);
-  const int jo = kTabCentral - 127 * kTabPerOct + (int)(__float_as_uint(v) >> (23 - kTabLogOct));
-  const int j = v < 1.0f ? jc : jo;
+  const double v = fabs(ax) * e.inv_w;  // a negative zero is the interval of 0
+  const int jc = min((int)fma(v, (double)kTabPerOct, 0.5), kTabPerOct);
+  const unsigned hi = (unsigned)(__double_as_longlong(v) >> 32);
+  const int jo = kTabCentral - 1023 * kTabPerOct + (int)(hi >> (20 - kTabLogOct));
+  const int j = max(jc, jo);
   return j < e.J - 1 ? j : e.J - 1;
 }
 
@@ -140,11 +144,14 @@ __device__ inline double div_nr(double n, double d) {
 // subtraction of values; there |ty| <= 1.5, a tenth of the radius of
 // convergence in units of the half-width).  Both forms are written as one
 // loop with the second row and argument chosen per lane (the compiler moves
-// the chain that a lane's form does not use into a branch).
+// the chain that a lane's form does not use into a branch).  The sign
+// flips are XORs of sign bits: x = |a|, y = +-b with the signs of a and of
+// the channel (pp: -b), and the result's sign by the channel.
 __device__ inline double K_eval(const Entry &e, const double *tab, int ch, double a, double b) {
-  const double y0 = ch ? b : -b;
-  const double f = a < 0.0 ? -1.0 : 1.0;
-  const double x = f * a, y = f * y0;
+  constexpr unsigned long long kSign = 0x8000000000000000ull;
+  const unsigned long long sc = ch ? 0ull : kSign;
+  const double x = fabs(a);
+  const double y = __longlong_as_double(__double_as_longlong(b) ^ (__double_as_longlong(a) & kSign) ^ sc);
   const double d = x - y;
   const bool close = d * d < kDdSwitch2 * (x * x + e.w * e.w);
   const double ay = fabs(y);
@@ -161,8 +168,9 @@ __device__ inline double K_eval(const Entry &e, const double *tab, int ch, doubl
     q = fma(q, tx, cx[k]);
     py = fma(py, ty, cy[k]);
   }
-  const double s = close ? r * rx[1] : div_nr(q - (y < 0.0 ? -py : py), d);
-  return ch ? s : -s;
+  const double sy = __longlong_as_double(__double_as_longlong(py) ^ (__double_as_longlong(y) & kSign));
+  const double s = close ? r * rx[1] : div_nr(q - sy, d);
+  return __longlong_as_double(__double_as_longlong(s) ^ sc);
 }
 
 }  // namespace paid

@@ -1119,7 +1119,9 @@ __device__ inline double wave_uniform(double v) {
 // One group of up to 8 work items of one parameter row (row entry erow,
 // table tab in LDS, the wave's LDS at Yw), first item g0 in slot s0; items
 // g0 + it >= gend are inactive (their lanes repeat the last item and store
-// nothing).
+// nothing).  BUB: the bubble integrands (kinds 0 and 1); otherwise the unit
+// integrand.
+template <bool BUB>
 __device__ void lpc_group(const Problem &P, int erow, const double *tab, double *Yw, int g0,
                           int gend, int s0) {
   using namespace lpc;
@@ -1223,6 +1225,10 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
     double cxv, sx;
     column_trig(a, cxv, sx);
     const double Cx = cLx * cxv - sLx * sx, Dx = cLx * cxv + sLx * sx;
+    // the energies along the column are affine in the row's cosine:
+    // -2t (Cx + py) - 4t' Cx py - mu = (-2t Cx - mu) + py (-2t - 4t' Cx)
+    const double Aa = fma(mt2, Cx, -E.mu), Ba = fma(mtp4, Cx, mt2);
+    const double Ab = fma(mt2, Dx, -E.mu), Bb = fma(mtp4, Dx, mt2);
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
       H2[k] = 0.0;
@@ -1232,12 +1238,7 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
     for (int b = b0; b < b1; ++b) {
       const double *row = Yc + b * kYRow;
       double g = 1.0;  // PAID_UNIT
-      if (P.kind <= 1) {
-        const double py = row[0], my = row[1];
-        const double ea = mt2 * (Cx + py) + mtp4 * Cx * py - E.mu;
-        const double eb = mt2 * (Dx + my) + mtp4 * Dx * my - E.mu;
-        g = K_eval(E, tab, chl, ea, eb);
-      }
+      if constexpr (BUB) g = K_eval(E, tab, chl, fma(row[0], Ba, Aa), fma(row[1], Bb, Ab));
       const double g2 = c_rule.w2[b] * g, g1 = ((b & 1) ? 0.0 : c_rule.w1[b >> 1]) * g;
       H2[0] += g2;
       H1[0] += g1;
@@ -1384,6 +1385,7 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
 // The same work partition and table staging as k_children; inside a segment
 // (items of one parameter row) wave wv takes the groups of 8 items that
 // start at seg + 8 (wv + nw k).
+template <bool BUB>
 __global__ void __launch_bounds__(512) k_children_lpc(Problem P) {
   extern __shared__ double lds_raw[];
   double *tabl = lds_raw;
@@ -1419,7 +1421,7 @@ __global__ void __launch_bounds__(512) k_children_lpc(Problem P) {
         s = a;
         hi = P.woff[s + 1];
       }
-      lpc_group(kernarg_problem(P), e, tabl, Yw, g, seg_hi, s);
+      lpc_group<BUB>(kernarg_problem(P), e, tabl, Yw, g, seg_hi, s);
     }
     seg = seg_hi;
     if (seg < i1) {
@@ -1496,20 +1498,27 @@ int lpc_wave_doubles(const Problem &p) {
 // fits the device's per-workgroup limit) is the one that keeps the most
 // waves resident per CU, by the runtime's occupancy calculator; the choice
 // is remembered per table and wave size.
+// the two-lanes-per-child kernel for the problem's integrand
+const void *lpc_kernel(const Problem &p) {
+  return p.kind <= 1 ? reinterpret_cast<const void *>(&k_children_lpc<true>)
+                     : reinterpret_cast<const void *>(&k_children_lpc<false>);
+}
+
 size_t lpc_lds(const Problem &p, int *waves_out) {
   const size_t wave_b = sizeof(double) * lpc_wave_doubles(p);
   const size_t tab_b = sizeof(double) * (size_t)p.tab_rows * kTabStride;
   const size_t limit = p.lds_limit > 0 ? (size_t)p.lds_limit : 65536;
   thread_local size_t memo_tab = 0, memo_wave = 0, memo_limit = 0;
   thread_local int memo_waves = 0;
-  if (memo_waves == 0 || memo_tab != tab_b || memo_wave != wave_b || memo_limit != limit) {
+  thread_local const void *memo_kern = nullptr;
+  if (memo_waves == 0 || memo_tab != tab_b || memo_wave != wave_b || memo_limit != limit ||
+      memo_kern != lpc_kernel(p)) {
     int best = 0, best_w = 0;
     for (int w : {4, 6, 8, 2, 1}) {
       const size_t sh = tab_b + (size_t)w * wave_b;
       if (sh > limit || (best > 0 && w < 4)) continue;
       int n = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &n, reinterpret_cast<const void *>(&k_children_lpc), 64 * w, sh) != hipSuccess)
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lpc_kernel(p), 64 * w, sh) != hipSuccess)
         n = 0;
       if (n < 1) n = (w < 4 && best == 0) ? 1 : 0;  // a last resort still runs
       if (n * w > best) {
@@ -1519,6 +1528,7 @@ size_t lpc_lds(const Problem &p, int *waves_out) {
     }
     if (best_w == 0) return 0;
     memo_tab = tab_b;
+    memo_kern = lpc_kernel(p);
     memo_wave = wave_b;
     memo_limit = limit;
     memo_waves = best_w;
@@ -1594,8 +1604,7 @@ int eval_occupancy(const Problem &p) {
     int waves = 0, n = 0;
     const size_t sh = lpc_lds(p, &waves);
     if (sh == 0) return 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_children_lpc),
-                                                     64 * waves, sh) != hipSuccess || n < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lpc_kernel(p), 64 * waves, sh) != hipSuccess || n < 1)
       n = 1;
     return n;
   }
@@ -1613,7 +1622,10 @@ hipError_t launch_eval(const Problem &p, int grid, hipStream_t s) {
     if (sh == 0) return hipErrorInvalidValue;
     Problem q = p;
     q.lds_wave_doubles = lpc_wave_doubles(p);
-    hipLaunchKernelGGL(k_children_lpc, dim3(grid), dim3(64 * waves), sh, s, q);
+    if (p.kind <= 1)
+      hipLaunchKernelGGL(k_children_lpc<true>, dim3(grid), dim3(64 * waves), sh, s, q);
+    else
+      hipLaunchKernelGGL(k_children_lpc<false>, dim3(grid), dim3(64 * waves), sh, s, q);
     return hipGetLastError();
   }
   switch (p.L) {

@@ -8,10 +8,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_flop_count_per_item():
-    # integrand 289 x 80, separable projection for 9 form factors 13,176
-    assert bench.item_flops(9, 1, True) == 289 * 80 + 13176 == 36296
+    # integrand 289 x 72 + 17 columns x 8, separable projection for 9 form factors 13,176
+    assert bench.item_flops(9, 1, True) == 289 * 72 + 17 * 8 + 13176 == 34120
     # dense Gram: 4 children x 2 M^2 (81 + 25)
-    assert bench.item_flops(25, 2, False) == 289 * 80 + 4 * 2 * 625 * 106
+    assert bench.item_flops(25, 2, False) == 289 * 72 + 17 * 8 + 4 * 2 * 625 * 106
 
 
 def test_traffic_belongs_to_the_profiled_kernel():
