@@ -532,11 +532,14 @@ __device__ void transform_ff(WaveLds<L> &S, const Problem &P) {
 }
 
 // a double moved between lanes by a DPP pattern (both halves; VALU, no LDS)
+// v from another lane of the same row (CTRL: a quad permutation or a row
+// mirror, which every lane reads within its row, so no lane keeps an old
+// value and none need be set up)
 template <int CTRL>
 __device__ inline double dpp_move(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -1120,8 +1123,10 @@ __device__ inline double wave_uniform(double v) {
 // table tab in LDS, the wave's LDS at Yw), first item g0 in slot s0; items
 // g0 + it >= gend are inactive (their lanes repeat the last item and store
 // nothing).  BUB: the bubble integrands (kinds 0 and 1); otherwise the unit
-// integrand.
-template <bool BUB>
+// integrand.  WE: per-pair errors are stored (FP32 records and deltas);
+// otherwise the children's errors only form their keys.  WW: the keys weigh
+// the pairs (per-integral and weighted modes); otherwise they are plain sums.
+template <bool BUB, bool WE, bool WW>
 __device__ void lpc_group(const Problem &P, int erow, const double *tab, double *Yw, int g0,
                           int gend, int s0) {
   using namespace lpc;
@@ -1336,12 +1341,13 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
   const double pkey = P.key[q.pbase];
   const double wdt = kTwoPi * ldexp(1.0, -dd);
   const double fa = (0.25 * wdt) * (0.25 * wdt) / (4.0 * kPi * kPi);
+  const double fx = phc ? 0.0 : fa;  // placeholders store zeros
   const long ri = (ch == 0) ? q.leaf : (long)P.nleaf[q.s] + 3L * q.r + (ch - 1);
   const long base = slot_base(P, q.s) + ri;
   const long itm = (long)q.s * P.bmax + q.r;
   const bool head = valid && ch == 0;
   const double *par = (h ? PE : PQ) + it * lpc::kPairs;
-  const double *wgt = P.err_mode != 0 ? PW + it * lpc::kPairs : nullptr;
+  [[maybe_unused]] const double *wgt = P.err_mode != 0 ? PW + it * lpc::kPairs : nullptr;
   double *dst = h ? P.dep : P.dv;
   double key = 0.0;
   constexpr lpc::PairTab PT = lpc::make_pair_tab();
@@ -1355,17 +1361,23 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
       if (tp[4] >= 0) u = tp[5] > 0 ? u + I[tp[1]][tp[4]] : u - I[tp[1]][tp[4]];
       v = tp[2] > 0 ? v + u : v - u;
     }
-    const double x = phc ? 0.0 : fa * v;  // lane 0: Q_2N of the pair, lane 1: E
+    const double x = fx * v;  // lane 0: Q_2N of the pair, lane 1: E
     const double e = fabs(x);
-    const float ef = err_f32(e);
-    key += wgt ? e * wgt[p] : e;
-    if (h == 0) {
-      if (valid) P.Q[base * MU + p] = x;
-    } else if (valid && P.E) {
-      P.E[base * MU + p] = ef;
+    if constexpr (WW)
+      key += wgt ? e * wgt[p] : e;  // (the test keeps the weights' loads where they are used)
+    else
+      key += e;
+    // lane 1's term of the children's sum: the same float-rounded error
+    // that is stored and later subtracted (without stored errors lane 1's
+    // sum is not used)
+    double term = x;
+    if constexpr (WE) {
+      const float ef = err_f32(e);
+      if (h == 1 && valid) P.E[base * MU + p] = ef;
+      if (h) term = (double)ef;
     }
-    // the same float-rounded error that is stored and later subtracted
-    const double sum = lpc::child_sum(h ? (double)ef : x);
+    if (h == 0 && valid) P.Q[base * MU + p] = x;
+    const double sum = lpc::child_sum(term);
     if (head && dst) dst[itm * MU + p] = sum - par[p];
   }
   // child keys (lane 1) and the item's key delta
@@ -1385,7 +1397,7 @@ __device__ void lpc_group(const Problem &P, int erow, const double *tab, double 
 // The same work partition and table staging as k_children; inside a segment
 // (items of one parameter row) wave wv takes the groups of 8 items that
 // start at seg + 8 (wv + nw k).
-template <bool BUB>
+template <bool BUB, bool WE, bool WW>
 __global__ void __launch_bounds__(512) k_children_lpc(Problem P) {
   extern __shared__ double lds_raw[];
   double *tabl = lds_raw;
@@ -1421,7 +1433,7 @@ __global__ void __launch_bounds__(512) k_children_lpc(Problem P) {
         s = a;
         hi = P.woff[s + 1];
       }
-      lpc_group<BUB>(kernarg_problem(P), e, tabl, Yw, g, seg_hi, s);
+      lpc_group<BUB, WE, WW>(kernarg_problem(P), e, tabl, Yw, g, seg_hi, s);
     }
     seg = seg_hi;
     if (seg < i1) {
@@ -1500,8 +1512,16 @@ int lpc_wave_doubles(const Problem &p) {
 // is remembered per table and wave size.
 // the two-lanes-per-child kernel for the problem's integrand
 const void *lpc_kernel(const Problem &p) {
-  return p.kind <= 1 ? reinterpret_cast<const void *>(&k_children_lpc<true>)
-                     : reinterpret_cast<const void *>(&k_children_lpc<false>);
+  static const void *const k[8] = {
+      reinterpret_cast<const void *>(&k_children_lpc<false, false, false>),
+      reinterpret_cast<const void *>(&k_children_lpc<false, false, true>),
+      reinterpret_cast<const void *>(&k_children_lpc<false, true, false>),
+      reinterpret_cast<const void *>(&k_children_lpc<false, true, true>),
+      reinterpret_cast<const void *>(&k_children_lpc<true, false, false>),
+      reinterpret_cast<const void *>(&k_children_lpc<true, false, true>),
+      reinterpret_cast<const void *>(&k_children_lpc<true, true, false>),
+      reinterpret_cast<const void *>(&k_children_lpc<true, true, true>)};
+  return k[(p.kind <= 1 ? 4 : 0) + (p.E ? 2 : 0) + (p.err_mode != 0 ? 1 : 0)];
 }
 
 size_t lpc_lds(const Problem &p, int *waves_out) {
@@ -1622,10 +1642,9 @@ hipError_t launch_eval(const Problem &p, int grid, hipStream_t s) {
     if (sh == 0) return hipErrorInvalidValue;
     Problem q = p;
     q.lds_wave_doubles = lpc_wave_doubles(p);
-    if (p.kind <= 1)
-      hipLaunchKernelGGL(k_children_lpc<true>, dim3(grid), dim3(64 * waves), sh, s, q);
-    else
-      hipLaunchKernelGGL(k_children_lpc<false>, dim3(grid), dim3(64 * waves), sh, s, q);
+    void *args[] = {&q};
+    const hipError_t e = hipLaunchKernel(lpc_kernel(p), dim3(grid), dim3(64 * waves), args, sh, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
   }
   switch (p.L) {
