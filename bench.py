@@ -69,8 +69,8 @@ K_FLOPS_PER_COLUMN = 8
 # FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy's readings
 # (profiles/k_children_c2_counters.md); valid only for the kernel they were
 # taken with, identified by this hash of the two files that define it.
-TRAFFIC_BYTES_PER_ITEM = 2514
-TRAFFIC_SOURCES_SHA256 = "bfa2bc60968e32d0703060ed8653636d7f8c476e52c6af189c636ba0f9c993b9"
+TRAFFIC_BYTES_PER_ITEM = 2471
+TRAFFIC_SOURCES_SHA256 = "72f43a61f2f7d824f78660c0e192a3f483e22e6bb9ae10837f50923c3a6f2734"
 NODES_PER_ITEM = 289
 
 # Per-workload region budget (max_regions): the smallest power of two that
