@@ -108,3 +108,38 @@ def test_key_bins_stay_a_quarter_octave_wide_below_the_normal_range():
             assert key_bin(math.ldexp(k, -e), eb) == 4 * jj, (maxkey, jj)
             if k >= 2.3e-308 and maxkey >= 2.3e-308:
                 assert key_bin(k, bits(maxkey) >> 50) == 4 * jj
+
+
+def test_table_interval_index_needs_no_compare():
+    """The frequency-sum table's interval of v = |x| / w: central intervals
+    round(8 v) for v < 1, then 8 per octave (9 + 8 floor(log2 v) + the top
+    three mantissa bits).  The device forms the central candidate capped at
+    8 and the octave candidate from the high word of the double, and takes
+    the larger: for v < 1 the octave candidate is never above the central one,
+    for v >= 1 it is at least 9.  Checked here against the definition (the
+    same arithmetic as the kernel, in Python), negative zero included."""
+    import math
+    import struct
+
+    def device(x):
+        v = abs(x)  # the kernel takes |x| (a negative zero is the interval of 0)
+        jc = min(int(math.floor(v * 8 + 0.5)) if v < 2.0 ** 31 else 2 ** 31 - 1, 8)
+        hi = struct.unpack("<Q", struct.pack("<d", v))[0] >> 32
+        jo = 9 - 1023 * 8 + (hi >> 17)
+        return max(jc, jo)
+
+    def definition(x):
+        v = abs(x)
+        if v < 1.0:
+            return int(math.floor(v * 8 + 0.5))
+        e = math.frexp(v)[1] - 1  # floor(log2 v)
+        m = int(math.floor((v / 2.0 ** e - 1.0) * 8))
+        return 9 + 8 * e + m
+
+    vals = [0.0, -0.0, 5e-324, 1e-300, 0.0625, 0.0624999, 0.5, 0.9375, 0.99999999,
+            1.0, 1.0000001, 1.125, 1.999999, 2.0, 3.0, 1023.9, 1e6, 1e30]
+    vals += [k / 64.0 for k in range(0, 200)]
+    vals += [2.0 ** k * (1 + j / 8.0) for k in range(0, 40) for j in range(8)]
+    for x in vals:
+        assert device(x) == definition(x), x
+        assert device(-x) == definition(x), -x
