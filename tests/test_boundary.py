@@ -143,3 +143,48 @@ def test_table_interval_index_needs_no_compare():
     for x in vals:
         assert device(x) == definition(x), x
         assert device(-x) == definition(x), -x
+
+
+def test_kernel_sign_flips_by_xor_match_the_products():
+    """K_j(a, b) flips both energies to x >= 0 (S is odd, S[x,y] = S[-x,-y]):
+    the kernel forms x = |a| and y = +-b by XOR of sign bits (the sign of a,
+    and of the channel: pp takes -b), where the plain form is f a and f y0
+    with f = sign(a) and y0 = b (ph) or -b (pp).  Both agree for every
+    nonzero a (a zero a is an even point of S and the two forms differ only
+    in the sign of that zero)."""
+    import struct
+
+    def bits(v):
+        return struct.unpack("<Q", struct.pack("<d", v))[0]
+
+    def dbl(b):
+        return struct.unpack("<d", struct.pack("<Q", b))[0]
+
+    SIGN = 1 << 63
+    for a in [-3.5, -1e-300, -2.0 ** -1074, 1e-300, 0.25, 7.0, -0.125]:
+        for b in [-2.0, -0.0, 0.0, 1e-310, 3.0]:
+            for ch in (0, 1):
+                sc = 0 if ch else SIGN
+                x = abs(a)
+                y = dbl(bits(b) ^ (bits(a) & SIGN) ^ sc)
+                f = -1.0 if a < 0 else 1.0
+                y0 = b if ch else -b
+                assert x == f * a and bits(y) == bits(f * y0), (a, b, ch)
+
+
+def test_node_energies_are_affine_along_a_column():
+    """Along a node column the energy -2t (cx + cy) - 4t' cx cy - mu is affine in
+    the row's cosine cy: (-2t cx - mu) + cy (-2t - 4t' cx); the kernel forms
+    the two coefficients once per column and one FMA per node.  Checked
+    against the plain form to rounding over the workloads' parameter ranges."""
+    import numpy as np
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        t, tp, mu = 1.0, rng.uniform(-0.35, 0.0), rng.uniform(-1.2, 0.2)
+        cx = rng.uniform(-1, 1)
+        cy = rng.uniform(-1, 1, 64)
+        plain = -2 * t * (cx + cy) - 4 * tp * cx * cy - mu
+        A, B = -2 * t * cx - mu, -2 * t - 4 * tp * cx
+        affine = A + cy * B
+        scale = 2 * abs(t) * 2 + 4 * abs(tp) + abs(mu)
+        assert np.abs(affine - plain).max() <= 8 * np.finfo(float).eps * scale
