@@ -58,9 +58,10 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64: vector (256 CUs x 4 SIMD x 16 lanes x 2 
 #     x-sums  4 children x NP^2 x 42 (fine 9 x (mul + FMA), coarse 5 x (mul + FMA))
 #     pairs   4 children x MB(MB+1)/2 x 3
 #   dense projection (matrix cores): 4 children x 2 M^2 (81 + 25).
-# This is the method's work; an implementation that forms the same sums in
-# fewer operations (another basis of the axis products, edges evaluated once
-# per child) is credited with this count, not with its own.
+# This is the method's work in the cheapest form of each step the library
+# uses (the separable projection, the per-column energies); work an
+# implementation adds (shared edge nodes evaluated once per child: 324 node
+# evaluations instead of 289) is not counted.
 K_FLOPS_PER_NODE = 72
 COLUMNS_PER_ITEM = 17
 K_FLOPS_PER_COLUMN = 8
